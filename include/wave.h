@@ -1,0 +1,159 @@
+/*
+ * wave.h -- C ABI of the MI355X (gfx950) acoustic finite-difference solver.
+ *
+ * The solver integrates the isotropic acoustic wave equation with a source term
+ * and zero initial state (paper Section 2.1, Eq. (1)), m = 1/v^2, extended by the
+ * damping term of the paper's damped SO2 propagation listing (Section 2.1):
+ *
+ *     m u_tt + m gamma u_t - lap(u) = q_s .
+ *
+ * Discretisation (second-order leapfrog in time, the listing's form divided by
+ * its denominator r0):
+ *
+ *     u^{n+1} = ( 2u^n - (1-b) u^{n-1} + dt^2 v^2 ( L_h u^n + P^T s^n ) ) / (1+b)
+ *     b = dt gamma / 2,     d^n = R u^{n+1}
+ *
+ * L_h: star Laplacian of even space order SO = 2r (2..16), weights of the centred
+ * second-derivative stencil, values outside the grid are zero (an r-wide zero
+ * halo). gamma = gamma_x(i) + gamma_y(j) + gamma_z(k); on a face of width nbl the
+ * d-th point from the outside (d = 0..nbl-1) has p = (nbl-d)/nbl and
+ * gamma = gmax (p - sin(2 pi p)/(2 pi)), gmax = 3 vmax ln(1000) / (2 nbl h).
+ * P / R: trilinear injection / interpolation at off-grid points (exact on
+ * grid points). Source sample s^n (t = n dt) drives the equation that produces
+ * u^{n+1}; receivers record d^n = R u^{n+1}, n = 0..nt-1.
+ *
+ * Backward propagation (paper's conclusion, future work there) is the exact
+ * transpose of the forward map s -> d; the gradient is that of a loss L(d) given
+ * dL/dd, with respect to velocity (and to the wavelet).
+ *
+ * Conventions for every entry point:
+ *  - Arrays are x-fastest: element (i,j,k) of an nx*ny*nz field is at
+ *    (k*ny + j)*nx + i; grid point (i,j,k) sits at (i*hx, j*hy, k*hz) metres.
+ *  - Pointers named *_h are host memory, read only during the call. All other
+ *    array pointers are device memory owned by the caller.
+ *  - The caller owns the workspace (device, 256-byte aligned, at least
+ *    wave_workspace_bytes()). Solver calls allocate no device memory.
+ *  - Work is enqueued on `hip_stream` (a hipStream_t, NULL = the default
+ *    stream) and the call returns; outputs are valid after that stream
+ *    synchronises. Calls on distinct (workspace, stream) pairs may run
+ *    concurrently; calls sharing a workspace must be ordered on one stream.
+ *  - Validation is synchronous and happens before anything is enqueued; on
+ *    error nothing is enqueued and no output is touched. No exception crosses
+ *    the ABI.
+ */
+#ifndef WAVE_H
+#define WAVE_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* Status codes (int return values). */
+#define WAVE_OK 0
+#define WAVE_EINVAL (-1)  /* bad argument: sizes, space order, null pointer, point off grid */
+#define WAVE_ECFL (-2)    /* dt above the stability limit wave_cfl_dt_max()                 */
+#define WAVE_ENOMEM (-3)  /* workspace smaller than wave_workspace_bytes()                  */
+#define WAVE_EDEVICE (-4) /* a HIP runtime call failed                                      */
+#define WAVE_EBUSY (-5)   /* serving engine: request exceeds the memory budget              */
+#define WAVE_EAGAIN (-6)  /* serving engine: result not ready yet                           */
+
+/* Wavefield storage formats (arithmetic is FP32 in every format). */
+#define WAVE_STORE_F32 0
+#define WAVE_STORE_F16 1
+#define WAVE_STORE_BF16 2
+
+/* Workspace modes for wave_workspace_bytes(). */
+#define WAVE_MODE_FORWARD 0
+#define WAVE_MODE_ADJOINT 1
+#define WAVE_MODE_GRADIENT 2
+
+typedef struct {
+  int32_t nx, ny, nz;  /* grid points per axis, sponge included                       */
+  double hx, hy, hz;   /* spacing [m]                                                 */
+  int32_t so;          /* space order, even, 2..16 (stencil radius so/2)              */
+  double dt;           /* time step [s], at most wave_cfl_dt_max(so, vmax, hx, hy, hz) */
+  int32_t nt;          /* number of time steps (>= 0)                                 */
+  int32_t nbl[6];      /* sponge width per face: x-, x+, y-, y+, z-, z+ (0 = none)    */
+  double vmax;         /* velocity bound [m/s]: max(vel) <= vmax is the caller's
+                          promise; sets the sponge strength and the dt check         */
+  int32_t storage;     /* WAVE_STORE_*                                                */
+} wave_grid;
+
+/* Largest stable dt of the leapfrog scheme (von Neumann):
+ * 2 / (vmax sqrt(S (hx^-2 + hy^-2 + hz^-2))), S = |w0| + 2 sum_q |w_q| the
+ * stencil's symbol at the Nyquist wavenumber. Returns a negative value for an
+ * invalid space order or non-positive arguments. */
+double wave_cfl_dt_max(int so, double vmax, double hx, double hy, double hz);
+
+/* Device workspace bytes needed by one call of the given mode for this grid,
+ * number of sources and receivers, and checkpoint interval (mode GRADIENT
+ * only; <= 0 means the interval used internally, 50). Returns 0 for an
+ * invalid grid. */
+size_t wave_workspace_bytes(const wave_grid* g, int nsrc, int nrec, int mode, int ckpt_every);
+
+/* Bytes of the checkpoint buffer that wave_forward fills and wave_gradient
+ * reads: ceil(nt / ckpt_every) pairs (u^{kC}, u^{kC-1}) of nx*ny*nz floats.
+ * Returns 0 when ckpt_every <= 0 or the grid is invalid. */
+size_t wave_checkpoint_bytes(const wave_grid* g, int ckpt_every);
+
+/* Forward propagation (Eq. (1) with damping, source injection and receiver
+ * sampling).
+ *   vel       [nz][ny][nx] velocity m/s (device, FP32)
+ *   wavelet   [nt][nsrc] source samples (device; may be NULL when nsrc == 0)
+ *   src_xyz_h [nsrc][3] source positions in metres (host FP64)
+ *   rec_xyz_h [nrec][3] receiver positions in metres (host FP64)
+ *   rec_out   [nt][nrec] receives d^n (device; may be NULL when nrec == 0)
+ *   u0, um1   optional initial levels u^0, u^{-1} [nz][ny][nx] (NULL = 0)
+ *   u_final   optional [nz][ny][nx] receives u^{nt}
+ *   ckpt      optional checkpoint buffer (wave_checkpoint_bytes) receiving
+ *             (u^{kC}, u^{kC-1}) for k = 0..ceil(nt/C)-1, C = ckpt_every
+ * Returns WAVE_OK or a negative status. */
+int wave_forward(const wave_grid* g, const float* vel, const float* wavelet,
+                 const double* src_xyz_h, int nsrc, const double* rec_xyz_h, int nrec,
+                 float* rec_out, const float* u0, const float* um1, float* u_final,
+                 float* ckpt, int ckpt_every, void* workspace, size_t ws_bytes,
+                 void* hip_stream);
+
+/* Backward propagation: the exact transpose of wave_forward's map from
+ * wavelet to receiver data (zero initial state). Runs
+ *   lambda^n = (2 l^{n+1} - (1-b) l^{n+2} + dt^2 v^2 (L_h l^{n+1} + R^T d^n)) / (1+b)
+ * for n = nt-1..0 from lambda^{nt} = lambda^{nt+1} = 0 and samples
+ * src_out^n = P lambda^n.
+ *   rec_data  [nt][nrec] (device), src_out [nt][nsrc] (device, may be NULL
+ *   when nsrc == 0), lam_final optional [nz][ny][nx] receives lambda^0. */
+int wave_adjoint(const wave_grid* g, const float* vel, const float* rec_data,
+                 const double* rec_xyz_h, int nrec, const double* src_xyz_h, int nsrc,
+                 float* src_out, float* lam_final, void* workspace, size_t ws_bytes,
+                 void* hip_stream);
+
+/* Gradient of a loss L(d) of the forward receiver data d, given
+ * rec_grad = dL/dd [nt][nrec] (for the least-squares misfit: d - d_obs).
+ * With lambda from wave_adjoint driven by rec_grad,
+ *   dL/dm = -sum_n lambda^n ( (u^{n+1} - 2u^n + u^{n-1})/dt^2
+ *                             + gamma (u^{n+1} - u^{n-1})/(2 dt) ),
+ *   grad_vel = dL/dv = -2 v^-3 dL/dm     (gamma held fixed),
+ *   grad_wavelet^n = dL/ds^n = P lambda^n (optional, may be NULL).
+ * Forward levels come from ckpt (filled by wave_forward with the same
+ * ckpt_every) or, when ckpt is NULL, from an internal forward pass that keeps
+ * checkpoints in the workspace; each segment of ckpt_every steps is recomputed
+ * before its adjoint steps. */
+int wave_gradient(const wave_grid* g, const float* vel, const float* wavelet,
+                  const double* src_xyz_h, int nsrc, const double* rec_xyz_h, int nrec,
+                  const float* rec_grad, const float* ckpt, int ckpt_every,
+                  float* grad_vel, float* grad_wavelet, void* workspace, size_t ws_bytes,
+                  void* hip_stream);
+
+/* Human-readable name of a status code (static string). */
+const char* wave_status_string(int status);
+
+/* Library version string (static). */
+const char* wave_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* WAVE_H */

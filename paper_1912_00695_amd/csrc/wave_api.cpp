@@ -1,0 +1,618 @@
+// wave_api.cpp -- host runtime behind include/wave.h: argument validation,
+// workspace layout, injection/sampling tables, and the time-loop drivers of
+// the forward, adjoint and gradient solves.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdlib>
+#include <cstring>
+#include <map>
+#include <vector>
+
+#include "../../include/wave.h"
+#include "wave_internal.h"
+
+namespace wave {
+namespace {
+
+constexpr size_t kAlign = 256;
+constexpr int kDefaultCkpt = 50;
+
+size_t align_up(size_t v) { return (v + kAlign - 1) / kAlign * kAlign; }
+
+// Centred second-derivative weights of order 2r, closed form:
+// w_q = 2 (-1)^{q+1} (r!)^2 / (q^2 (r-q)! (r+q)!), w_0 = -2 sum_q 1/q^2.
+void fd_weights(int so, double* w) {
+  const int r = so / 2;
+  double s = 0.0;
+  for (int q = 1; q <= r; ++q) {
+    // (r!)^2 / ((r-q)! (r+q)!) = prod_{i=1..q} (r-q+i) / (r+i)
+    double ratio = 1.0;
+    for (int i = 1; i <= q; ++i) ratio *= (double)(r - q + i) / (double)(r + i);
+    w[q] = 2.0 * ((q % 2) ? 1.0 : -1.0) * ratio / ((double)q * q);
+    s += 1.0 / ((double)q * q);
+  }
+  w[0] = -2.0 * s;
+}
+
+bool grid_ok(const wave_grid* g) {
+  if (g == nullptr) return false;
+  if (g->nx < 1 || g->ny < 1 || g->nz < 1) return false;
+  if (g->so < 2 || g->so > 2 * MAXR || g->so % 2) return false;
+  if (!(g->hx > 0 && g->hy > 0 && g->hz > 0 && g->dt > 0 && g->vmax > 0)) return false;
+  if (!std::isfinite(g->hx) || !std::isfinite(g->hy) || !std::isfinite(g->hz) ||
+      !std::isfinite(g->dt) || !std::isfinite(g->vmax))
+    return false;
+  if (g->nt < 0) return false;
+  const int n[3] = {g->nx, g->ny, g->nz};
+  for (int a = 0; a < 3; ++a) {
+    if (g->nbl[2 * a] < 0 || g->nbl[2 * a + 1] < 0) return false;
+    if (g->nbl[2 * a] + g->nbl[2 * a + 1] > n[a]) return false;
+  }
+  if (g->storage != WAVE_STORE_F32) return false;
+  const int64_t pitch = (g->nx + 31) / 32 * 32;
+  if (pitch * g->ny * (int64_t)g->nz >= ((int64_t)1 << 31)) return false;
+  return true;
+}
+
+Geom make_geom(const wave_grid* g) {
+  Geom G;
+  G.nx = g->nx; G.ny = g->ny; G.nz = g->nz;
+  G.pitch = (g->nx + 31) / 32 * 32;
+  G.plane = (int64_t)G.pitch * G.ny;
+  G.nfield = G.plane * G.nz;
+  return G;
+}
+
+int env_int(const char* name, int dflt) {
+  const char* s = std::getenv(name);
+  if (s == nullptr || *s == 0) return dflt;
+  return std::atoi(s);
+}
+
+struct Tiling {
+  int ntile_x, ntile_y, nchunk, zchunk, nblocks;
+};
+
+// z-chunking: enough workgroups to fill 256 CUs several times over, chunks not
+// shorter than 4 planes. WAVE_ZCHUNK overrides the chunk length (tuning).
+Tiling make_tiling(const Geom& G) {
+  Tiling T;
+  T.ntile_x = (G.nx + TX - 1) / TX;
+  T.ntile_y = (G.ny + TY - 1) / TY;
+  const int bxy = T.ntile_x * T.ntile_y;
+  int zc = env_int("WAVE_ZCHUNK", 0);
+  if (zc <= 0) {
+    const int want = std::max(1, (1024 + bxy - 1) / bxy);
+    zc = (G.nz + want - 1) / want;
+    zc = std::max(zc, 4);
+  }
+  zc = std::min(zc, G.nz);
+  T.zchunk = zc;
+  T.nchunk = (G.nz + zc - 1) / zc;
+  T.nblocks = bxy * T.nchunk;
+  return T;
+}
+
+int64_t max_tiles(const Geom& G) {
+  return (int64_t)((G.nx + TX - 1) / TX) * ((G.ny + TY - 1) / TY) * G.nz;
+}
+
+// ---------------------------------------------------------------------------
+// Workspace layout.
+struct PointTables {   // offsets into the workspace
+  size_t tile_beg, ent, csr_idx, csr_w, samp_idx, samp_w;
+};
+
+struct Layout {
+  size_t c2, bx, by, bz, u[2];
+  PointTables pts[2];  // 0: sources, 1: receivers
+  size_t tables_beg, tables_end;
+  size_t graw, lam[2], seg, ick;  // gradient mode
+  int ckpt_every, nseg;
+  size_t total;
+};
+
+Layout make_layout(const wave_grid* g, int nsrc, int nrec, int mode, int ckpt_every) {
+  const Geom G = make_geom(g);
+  Layout L{};
+  size_t off = 0;
+  auto take = [&](size_t bytes) { size_t o = off; off = align_up(off + bytes); return o; };
+  const size_t fbytes = (size_t)G.nfield * sizeof(float);
+  L.c2 = take(fbytes);
+  L.u[0] = take(fbytes);
+  L.u[1] = take(fbytes);
+  L.tables_beg = off;
+  L.bx = take((size_t)G.pitch * sizeof(float));
+  L.by = take((size_t)G.ny * sizeof(float));
+  L.bz = take((size_t)G.nz * sizeof(float));
+  const int64_t nt = max_tiles(G);
+  const int np[2] = {nsrc, nrec};
+  for (int s = 0; s < 2; ++s) {
+    const size_t n8 = (size_t)8 * std::max(np[s], 0);
+    L.pts[s].tile_beg = take((size_t)(nt + 1) * sizeof(int));
+    L.pts[s].ent = take(n8 * sizeof(InjEntry));
+    L.pts[s].csr_idx = take(n8 * sizeof(int));
+    L.pts[s].csr_w = take(n8 * sizeof(float));
+    L.pts[s].samp_idx = take(n8 * sizeof(int));
+    L.pts[s].samp_w = take(n8 * sizeof(float));
+  }
+  L.tables_end = off;
+  if (mode == WAVE_MODE_GRADIENT) {
+    const int C = ckpt_every > 0 ? ckpt_every : kDefaultCkpt;
+    L.ckpt_every = C;
+    L.nseg = g->nt > 0 ? (g->nt + C - 1) / C : 0;
+    const int seglen = std::min(C, std::max(g->nt, 1));
+    L.graw = take(fbytes);
+    L.lam[0] = take(fbytes);
+    L.lam[1] = take(fbytes);
+    L.seg = take(fbytes * (size_t)(seglen + 2));
+    L.ick = take(fbytes * (size_t)(2 * L.nseg));
+  }
+  L.total = off;
+  return L;
+}
+
+// ---------------------------------------------------------------------------
+// Trilinear corners of a point (metres); corners of weight exactly 0 dropped.
+// Returns false when the point lies outside [0, (n-1) h] on some axis.
+bool corners(const wave_grid* g, const double* xyz, int* ijk, double* w, int* cnt) {
+  const double f[3] = {xyz[0] / g->hx, xyz[1] / g->hy, xyz[2] / g->hz};
+  const int n[3] = {g->nx, g->ny, g->nz};
+  int i0[3];
+  double t[3];
+  for (int a = 0; a < 3; ++a) {
+    if (!(f[a] >= 0.0) || f[a] > (double)(n[a] - 1)) return false;
+    i0[a] = (int)std::floor(f[a]);
+    t[a] = f[a] - (double)i0[a];
+  }
+  int c = 0;
+  for (int dz = 0; dz < 2; ++dz)
+    for (int dy = 0; dy < 2; ++dy)
+      for (int dx = 0; dx < 2; ++dx) {
+        const double wt = (dx ? t[0] : 1.0 - t[0]) * (dy ? t[1] : 1.0 - t[1]) *
+                          (dz ? t[2] : 1.0 - t[2]);
+        if (wt == 0.0) continue;
+        ijk[3 * c + 0] = i0[0] + dx;
+        ijk[3 * c + 1] = i0[1] + dy;
+        ijk[3 * c + 2] = i0[2] + dz;
+        w[c] = wt;
+        ++c;
+      }
+  *cnt = c;
+  return true;
+}
+
+bool points_ok(const wave_grid* g, const double* xyz, int np) {
+  if (np < 0) return false;
+  if (np > 0 && xyz == nullptr) return false;
+  int ijk[24], c;
+  double w[8];
+  for (int p = 0; p < np; ++p)
+    if (!corners(g, xyz + 3 * p, ijk, w, &c)) return false;
+  return true;
+}
+
+// Host image of the table region, uploaded with one copy.
+struct Blob {
+  std::vector<char> bytes;
+  size_t base;
+  template <class T>
+  T* at(size_t off) { return reinterpret_cast<T*>(bytes.data() + (off - base)); }
+};
+
+void build_point_tables(const wave_grid* g, const Geom& G, const Tiling& T, const double* xyz,
+                        int np, const PointTables& P, Blob& B) {
+  int* tile_beg = B.at<int>(P.tile_beg);
+  const int ntiles = T.nblocks;
+  std::fill(tile_beg, tile_beg + ntiles + 1, 0);
+  // unique grid points -> ordered list of (point index, weight)
+  struct Key {
+    int tile, z, local;
+    bool operator<(const Key& o) const {
+      return tile != o.tile ? tile < o.tile : z != o.z ? z < o.z : local < o.local;
+    }
+  };
+  std::map<Key, std::vector<std::pair<int, float>>> uniq;
+  int* sidx = B.at<int>(P.samp_idx);
+  float* sw = B.at<float>(P.samp_w);
+  for (int p = 0; p < np; ++p) {
+    int ijk[24], c = 0;
+    double w[8];
+    corners(g, xyz + 3 * p, ijk, w, &c);
+    for (int k = 0; k < 8; ++k) {
+      sidx[8 * p + k] = 0;
+      sw[8 * p + k] = 0.f;
+    }
+    for (int k = 0; k < c; ++k) {
+      const int i = ijk[3 * k], j = ijk[3 * k + 1], z = ijk[3 * k + 2];
+      sidx[8 * p + k] = (int)((int64_t)z * G.plane + (int64_t)j * G.pitch + i);
+      sw[8 * p + k] = (float)w[k];
+      const int tile = ((z / T.zchunk) * T.ntile_y + j / TY) * T.ntile_x + i / TX;
+      const int local = (j % TY) * TX + (i % TX);
+      uniq[Key{tile, z, local}].push_back({p, (float)w[k]});
+    }
+  }
+  InjEntry* ent = B.at<InjEntry>(P.ent);
+  int* cidx = B.at<int>(P.csr_idx);
+  float* cw = B.at<float>(P.csr_w);
+  int e = 0, c = 0;
+  for (auto& kv : uniq) {
+    InjEntry en{};
+    en.z = kv.first.z;
+    en.local = kv.first.local;
+    en.csr_beg = c;
+    for (auto& pw : kv.second) {
+      cidx[c] = pw.first;
+      cw[c] = pw.second;
+      ++c;
+    }
+    en.csr_end = c;
+    ent[e] = en;
+    tile_beg[kv.first.tile + 1]++;
+    ++e;
+  }
+  for (int t = 0; t < ntiles; ++t) tile_beg[t + 1] += tile_beg[t];
+  // group ends: first entry of the next plane group within each tile
+  for (int t = 0; t < ntiles; ++t) {
+    int b = tile_beg[t], end = tile_beg[t + 1];
+    while (b < end) {
+      int q = b;
+      while (q < end && ent[q].z == ent[b].z) ++q;
+      for (int k = b; k < q; ++k) ent[k].grp_end = q;
+      b = q;
+    }
+  }
+}
+
+void sponge_1d(int n, int lo, int hi, double h, double vmax, double dt, float* b) {
+  const double pi = 3.14159265358979323846;
+  std::vector<double> gam(n, 0.0);
+  const int nbl[2] = {lo, hi};
+  for (int f = 0; f < 2; ++f) {
+    if (nbl[f] <= 0) continue;
+    const double gmax = 3.0 * vmax * std::log(1000.0) / (2.0 * nbl[f] * h);
+    for (int d = 0; d < nbl[f] && d < n; ++d) {
+      const double p = (double)(nbl[f] - d) / nbl[f];
+      gam[f == 0 ? d : n - 1 - d] += gmax * (p - std::sin(2.0 * pi * p) / (2.0 * pi));
+    }
+  }
+  for (int i = 0; i < n; ++i) b[i] = (float)(0.5 * dt * gam[i]);
+}
+
+void delete_blob(void* p) { delete static_cast<Blob*>(p); }
+
+// Common per-call state.
+struct Ctx {
+  const wave_grid* g;
+  Geom G;
+  Tiling T;
+  Layout L;
+  char* ws;
+  hipStream_t s;
+  double wx[MAXR + 1], wy[MAXR + 1], wz[MAXR + 1], wc;
+  template <class T>
+  T* at(size_t off) const { return reinterpret_cast<T*>(ws + off); }
+};
+
+#define HIP_TRY(x)                          \
+  do {                                      \
+    if ((x) != hipSuccess) return WAVE_EDEVICE; \
+  } while (0)
+
+int setup(Ctx& C, const wave_grid* g, const float* vel, const double* src, int nsrc,
+          const double* rec, int nrec, int mode, int ckpt_every, void* ws, size_t ws_bytes,
+          void* stream) {
+  C.g = g;
+  C.G = make_geom(g);
+  C.T = make_tiling(C.G);
+  C.L = make_layout(g, nsrc, nrec, mode, ckpt_every);
+  if (ws == nullptr || (reinterpret_cast<uintptr_t>(ws) % kAlign) != 0) return WAVE_EINVAL;
+  if (ws_bytes < C.L.total) return WAVE_ENOMEM;
+  C.ws = static_cast<char*>(ws);
+  C.s = static_cast<hipStream_t>(stream);
+  double w[MAXR + 1];
+  fd_weights(g->so, w);
+  const double ix = 1.0 / (g->hx * g->hx), iy = 1.0 / (g->hy * g->hy), iz = 1.0 / (g->hz * g->hz);
+  for (int q = 0; q <= MAXR; ++q) {
+    const double v = q <= g->so / 2 ? w[q] : 0.0;
+    C.wx[q] = v * ix; C.wy[q] = v * iy; C.wz[q] = v * iz;
+  }
+  C.wc = w[0] * (ix + iy + iz);
+  // host tables
+  Blob* B = new Blob;
+  B->base = C.L.tables_beg;
+  B->bytes.assign(C.L.tables_end - C.L.tables_beg, 0);
+  sponge_1d(g->nx, g->nbl[0], g->nbl[1], g->hx, g->vmax, g->dt, B->at<float>(C.L.bx));
+  sponge_1d(g->ny, g->nbl[2], g->nbl[3], g->hy, g->vmax, g->dt, B->at<float>(C.L.by));
+  sponge_1d(g->nz, g->nbl[4], g->nbl[5], g->hz, g->vmax, g->dt, B->at<float>(C.L.bz));
+  build_point_tables(g, C.G, C.T, src, nsrc, C.L.pts[0], *B);
+  build_point_tables(g, C.G, C.T, rec, nrec, C.L.pts[1], *B);
+  if (hipMemcpyAsync(C.ws + C.L.tables_beg, B->bytes.data(), B->bytes.size(),
+                     hipMemcpyHostToDevice, C.s) != hipSuccess) {
+    delete B;
+    return WAVE_EDEVICE;
+  }
+  if (hipLaunchHostFunc(C.s, delete_blob, B) != hipSuccess) {
+    (void)hipStreamSynchronize(C.s);
+    delete B;
+    return WAVE_EDEVICE;
+  }
+  HIP_TRY(launch_prep_c2(vel, C.at<float>(C.L.c2), C.G, g->dt, C.s));
+  return WAVE_OK;
+}
+
+StepArgs base_args(const Ctx& C) {
+  StepArgs a{};
+  a.c2 = C.at<float>(C.L.c2);
+  a.bx = C.at<float>(C.L.bx);
+  a.by = C.at<float>(C.L.by);
+  a.bz = C.at<float>(C.L.bz);
+  a.g = C.G;
+  a.ntile_x = C.T.ntile_x;
+  a.ntile_y = C.T.ntile_y;
+  a.nchunk = C.T.nchunk;
+  a.zchunk = C.T.zchunk;
+  a.nstencil_blocks = C.T.nblocks;
+  a.xcd_remap = env_int("WAVE_XCD_REMAP", 1) != 0;
+  for (int q = 0; q <= MAXR; ++q) {
+    a.wx[q] = (float)C.wx[q];
+    a.wy[q] = (float)C.wy[q];
+    a.wz[q] = (float)C.wz[q];
+  }
+  a.wc = (float)C.wc;
+  return a;
+}
+
+void set_inj(StepArgs& a, const Ctx& C, int set, int np, const float* row) {
+  if (np > 0 && row != nullptr) {
+    const PointTables& P = C.L.pts[set];
+    a.tile_beg = C.at<int>(P.tile_beg);
+    a.ent = C.at<InjEntry>(P.ent);
+    a.csr_idx = C.at<int>(P.csr_idx);
+    a.csr_w = C.at<float>(P.csr_w);
+    a.trace_row = row;
+  } else {
+    a.tile_beg = nullptr; a.ent = nullptr; a.csr_idx = nullptr; a.csr_w = nullptr;
+    a.trace_row = nullptr;
+  }
+}
+
+void set_samp(StepArgs& a, const Ctx& C, int set, int np, float* row) {
+  if (np > 0 && row != nullptr) {
+    const PointTables& P = C.L.pts[set];
+    a.samp_idx = C.at<int>(P.samp_idx);
+    a.samp_w = C.at<float>(P.samp_w);
+    a.nsamp = np;
+    a.samp_out = row;
+  } else {
+    a.samp_idx = nullptr; a.samp_w = nullptr; a.nsamp = 0; a.samp_out = nullptr;
+  }
+}
+
+int validate(const wave_grid* g) {
+  if (!grid_ok(g)) return WAVE_EINVAL;
+  const double dtm = wave_cfl_dt_max(g->so, g->vmax, g->hx, g->hy, g->hz);
+  if (!(g->dt <= dtm * (1.0 + 1e-12))) return WAVE_ECFL;
+  return WAVE_OK;
+}
+
+}  // namespace
+}  // namespace wave
+
+using namespace wave;
+
+extern "C" {
+
+double wave_cfl_dt_max(int so, double vmax, double hx, double hy, double hz) {
+  if (so < 2 || so > 2 * MAXR || so % 2 || !(vmax > 0) || !(hx > 0) || !(hy > 0) || !(hz > 0))
+    return -1.0;
+  double w[MAXR + 1];
+  fd_weights(so, w);
+  double S = std::fabs(w[0]);
+  for (int q = 1; q <= so / 2; ++q) S += 2.0 * std::fabs(w[q]);
+  return 2.0 / (vmax * std::sqrt(S * (1.0 / (hx * hx) + 1.0 / (hy * hy) + 1.0 / (hz * hz))));
+}
+
+size_t wave_workspace_bytes(const wave_grid* g, int nsrc, int nrec, int mode, int ckpt_every) {
+  if (!grid_ok(g) || nsrc < 0 || nrec < 0) return 0;
+  if (mode != WAVE_MODE_FORWARD && mode != WAVE_MODE_ADJOINT && mode != WAVE_MODE_GRADIENT)
+    return 0;
+  return make_layout(g, nsrc, nrec, mode, ckpt_every).total;
+}
+
+size_t wave_checkpoint_bytes(const wave_grid* g, int ckpt_every) {
+  if (!grid_ok(g) || ckpt_every <= 0) return 0;
+  const size_t n = (size_t)g->nx * g->ny * g->nz;
+  const size_t nck = g->nt > 0 ? (size_t)(g->nt + ckpt_every - 1) / ckpt_every : 0;
+  return nck * 2 * n * sizeof(float);
+}
+
+const char* wave_status_string(int status) {
+  switch (status) {
+    case WAVE_OK: return "ok";
+    case WAVE_EINVAL: return "invalid argument";
+    case WAVE_ECFL: return "time step above the stability limit";
+    case WAVE_ENOMEM: return "workspace too small";
+    case WAVE_EDEVICE: return "HIP runtime error";
+    case WAVE_EBUSY: return "over the memory budget";
+    case WAVE_EAGAIN: return "not ready";
+    default: return "unknown status";
+  }
+}
+
+const char* wave_version(void) { return "wave-gfx950 0.1"; }
+
+int wave_forward(const wave_grid* g, const float* vel, const float* wavelet,
+                 const double* src_xyz_h, int nsrc, const double* rec_xyz_h, int nrec,
+                 float* rec_out, const float* u0, const float* um1, float* u_final, float* ckpt,
+                 int ckpt_every, void* workspace, size_t ws_bytes, void* hip_stream) {
+  int st = validate(g);
+  if (st) return st;
+  if (vel == nullptr || nsrc < 0 || nrec < 0) return WAVE_EINVAL;
+  if (nsrc > 0 && wavelet == nullptr && g->nt > 0) return WAVE_EINVAL;
+  if (nrec > 0 && rec_out == nullptr && g->nt > 0) return WAVE_EINVAL;
+  if (!points_ok(g, src_xyz_h, nsrc) || !points_ok(g, rec_xyz_h, nrec)) return WAVE_EINVAL;
+  if (ckpt != nullptr && ckpt_every <= 0) return WAVE_EINVAL;
+  Ctx C;
+  st = setup(C, g, vel, src_xyz_h, nsrc, rec_xyz_h, nrec, WAVE_MODE_FORWARD, 0, workspace,
+             ws_bytes, hip_stream);
+  if (st) return st;
+  float* X[2] = {C.at<float>(C.L.u[0]), C.at<float>(C.L.u[1])};
+  HIP_TRY(launch_pack(u0, X[0], C.G, C.s));
+  HIP_TRY(launch_pack(um1, X[1], C.G, C.s));
+  const int64_t N = (int64_t)g->nx * g->ny * g->nz;
+  StepArgs a = base_args(C);
+  const int r = g->so / 2;
+  for (int n = 0; n < g->nt; ++n) {
+    float* cur = X[n & 1];
+    float* prev = X[(n + 1) & 1];
+    if (ckpt != nullptr && n % ckpt_every == 0) {
+      const int64_t k = n / ckpt_every;
+      HIP_TRY(launch_unpack(cur, ckpt + (2 * k) * N, C.G, C.s));
+      HIP_TRY(launch_unpack(prev, ckpt + (2 * k + 1) * N, C.G, C.s));
+    }
+    a.cur = cur;
+    a.prev = prev;
+    a.out = prev;
+    set_inj(a, C, 0, nsrc, nsrc > 0 ? wavelet + (int64_t)n * nsrc : nullptr);
+    set_samp(a, C, 1, nrec, n >= 1 && nrec > 0 ? rec_out + (int64_t)(n - 1) * nrec : nullptr);
+    HIP_TRY(launch_step(a, r, false, C.s));
+  }
+  if (nrec > 0 && g->nt > 0) {
+    const PointTables& P = C.L.pts[1];
+    HIP_TRY(launch_sample(X[g->nt & 1], C.at<int>(P.samp_idx), C.at<float>(P.samp_w), nrec,
+                          rec_out + (int64_t)(g->nt - 1) * nrec, C.s));
+  }
+  if (u_final != nullptr) HIP_TRY(launch_unpack(X[g->nt & 1], u_final, C.G, C.s));
+  return WAVE_OK;
+}
+
+int wave_adjoint(const wave_grid* g, const float* vel, const float* rec_data,
+                 const double* rec_xyz_h, int nrec, const double* src_xyz_h, int nsrc,
+                 float* src_out, float* lam_final, void* workspace, size_t ws_bytes,
+                 void* hip_stream) {
+  int st = validate(g);
+  if (st) return st;
+  if (vel == nullptr || nsrc < 0 || nrec < 0) return WAVE_EINVAL;
+  if (nrec > 0 && rec_data == nullptr && g->nt > 0) return WAVE_EINVAL;
+  if (nsrc > 0 && src_out == nullptr && g->nt > 0) return WAVE_EINVAL;
+  if (!points_ok(g, src_xyz_h, nsrc) || !points_ok(g, rec_xyz_h, nrec)) return WAVE_EINVAL;
+  Ctx C;
+  st = setup(C, g, vel, src_xyz_h, nsrc, rec_xyz_h, nrec, WAVE_MODE_ADJOINT, 0, workspace,
+             ws_bytes, hip_stream);
+  if (st) return st;
+  float* X[2] = {C.at<float>(C.L.u[0]), C.at<float>(C.L.u[1])};
+  HIP_TRY(launch_pack(nullptr, X[0], C.G, C.s));
+  HIP_TRY(launch_pack(nullptr, X[1], C.G, C.s));
+  StepArgs a = base_args(C);
+  const int r = g->so / 2;
+  const int nt = g->nt;
+  for (int n = nt - 1; n >= 0; --n) {
+    a.cur = X[(n + 1) & 1];
+    a.prev = X[n & 1];
+    a.out = X[n & 1];
+    set_inj(a, C, 1, nrec, nrec > 0 ? rec_data + (int64_t)n * nrec : nullptr);
+    set_samp(a, C, 0, nsrc,
+             (n + 1 <= nt - 1 && nsrc > 0) ? src_out + (int64_t)(n + 1) * nsrc : nullptr);
+    HIP_TRY(launch_step(a, r, false, C.s));
+  }
+  if (nsrc > 0 && nt > 0) {
+    const PointTables& P = C.L.pts[0];
+    HIP_TRY(launch_sample(X[0], C.at<int>(P.samp_idx), C.at<float>(P.samp_w), nsrc, src_out,
+                          C.s));
+  }
+  if (lam_final != nullptr) HIP_TRY(launch_unpack(X[0], lam_final, C.G, C.s));
+  return WAVE_OK;
+}
+
+int wave_gradient(const wave_grid* g, const float* vel, const float* wavelet,
+                  const double* src_xyz_h, int nsrc, const double* rec_xyz_h, int nrec,
+                  const float* rec_grad, const float* ckpt, int ckpt_every, float* grad_vel,
+                  float* grad_wavelet, void* workspace, size_t ws_bytes, void* hip_stream) {
+  int st = validate(g);
+  if (st) return st;
+  if (vel == nullptr || grad_vel == nullptr || nsrc < 0 || nrec < 0) return WAVE_EINVAL;
+  if (nsrc > 0 && wavelet == nullptr && g->nt > 0) return WAVE_EINVAL;
+  if (nrec > 0 && rec_grad == nullptr && g->nt > 0) return WAVE_EINVAL;
+  if (ckpt != nullptr && ckpt_every <= 0) return WAVE_EINVAL;
+  if (!points_ok(g, src_xyz_h, nsrc) || !points_ok(g, rec_xyz_h, nrec)) return WAVE_EINVAL;
+  Ctx C;
+  st = setup(C, g, vel, src_xyz_h, nsrc, rec_xyz_h, nrec, WAVE_MODE_GRADIENT, ckpt_every,
+             workspace, ws_bytes, hip_stream);
+  if (st) return st;
+  const int nt = g->nt, Cs = C.L.ckpt_every, r = g->so / 2;
+  const int64_t N = (int64_t)g->nx * g->ny * g->nz, F = C.G.nfield;
+  float* graw = C.at<float>(C.L.graw);
+  float* lam[2] = {C.at<float>(C.L.lam[0]), C.at<float>(C.L.lam[1])};
+  float* seg = C.at<float>(C.L.seg);
+  float* ick = C.at<float>(C.L.ick);
+  HIP_TRY(launch_pack(nullptr, graw, C.G, C.s));
+  HIP_TRY(launch_pack(nullptr, lam[0], C.G, C.s));
+  HIP_TRY(launch_pack(nullptr, lam[1], C.G, C.s));
+  StepArgs a = base_args(C);
+  if (ckpt == nullptr) {
+    // internal forward pass keeping (u^{kC}, u^{kC-1}) pitched in the workspace
+    float* X[2] = {C.at<float>(C.L.u[0]), C.at<float>(C.L.u[1])};
+    HIP_TRY(launch_pack(nullptr, X[0], C.G, C.s));
+    HIP_TRY(launch_pack(nullptr, X[1], C.G, C.s));
+    set_samp(a, C, 1, 0, nullptr);
+    for (int n = 0; n < nt; ++n) {
+      float* cur = X[n & 1];
+      float* prev = X[(n + 1) & 1];
+      if (n % Cs == 0) {
+        const int64_t k = n / Cs;
+        HIP_TRY(launch_copy(cur, ick + (2 * k) * F, F, C.s));
+        HIP_TRY(launch_copy(prev, ick + (2 * k + 1) * F, F, C.s));
+      }
+      a.cur = cur; a.prev = prev; a.out = prev;
+      set_inj(a, C, 0, nsrc, nsrc > 0 ? wavelet + (int64_t)n * nsrc : nullptr);
+      HIP_TRY(launch_step(a, r, false, C.s));
+    }
+  }
+  for (int s = C.L.nseg - 1; s >= 0; --s) {
+    const int n0 = s * Cs, n1 = std::min(n0 + Cs, nt);
+    // seg slot m holds u^{n0-1+m}
+    if (ckpt != nullptr) {
+      HIP_TRY(launch_pack(ckpt + (2 * (int64_t)s) * N, seg + 1 * F, C.G, C.s));
+      HIP_TRY(launch_pack(ckpt + (2 * (int64_t)s + 1) * N, seg + 0 * F, C.G, C.s));
+    } else {
+      HIP_TRY(launch_copy(ick + (2 * (int64_t)s) * F, seg + 1 * F, F, C.s));
+      HIP_TRY(launch_copy(ick + (2 * (int64_t)s + 1) * F, seg + 0 * F, F, C.s));
+    }
+    set_samp(a, C, 1, 0, nullptr);
+    a.ufwd = nullptr;
+    a.grad = nullptr;
+    for (int n = n0; n < n1; ++n) {
+      a.cur = seg + (int64_t)(n - n0 + 1) * F;
+      a.prev = seg + (int64_t)(n - n0) * F;
+      a.out = seg + (int64_t)(n - n0 + 2) * F;
+      set_inj(a, C, 0, nsrc, nsrc > 0 ? wavelet + (int64_t)n * nsrc : nullptr);
+      HIP_TRY(launch_step(a, r, false, C.s));
+    }
+    for (int n = n1 - 1; n >= n0; --n) {
+      a.cur = lam[(n + 1) & 1];
+      a.prev = lam[n & 1];
+      a.out = lam[n & 1];
+      a.ufwd = seg + (int64_t)(n - n0 + 2) * F;
+      a.grad = graw;
+      set_inj(a, C, 1, nrec, nrec > 0 ? rec_grad + (int64_t)n * nrec : nullptr);
+      set_samp(a, C, 0, nsrc,
+               (grad_wavelet != nullptr && nsrc > 0 && n + 1 <= nt - 1)
+                   ? grad_wavelet + (int64_t)(n + 1) * nsrc
+                   : nullptr);
+      HIP_TRY(launch_step(a, r, true, C.s));
+    }
+  }
+  if (grad_wavelet != nullptr && nsrc > 0 && nt > 0) {
+    const PointTables& P = C.L.pts[0];
+    HIP_TRY(launch_sample(lam[0], C.at<int>(P.samp_idx), C.at<float>(P.samp_w), nsrc,
+                          grad_wavelet, C.s));
+  }
+  // dL/dm = -graw / dt^2  ->  dL/dv = -2 v^-3 dL/dm = (2 / dt^2) graw / v^3
+  HIP_TRY(launch_grad_finalize(graw, vel, grad_vel, C.G, 2.0 / (g->dt * g->dt), C.s));
+  return WAVE_OK;
+}
+
+}  // extern "C"

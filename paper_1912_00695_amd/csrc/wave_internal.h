@@ -1,0 +1,89 @@
+// wave_internal.h -- data structures shared by the host runtime and the gfx950
+// kernels of the acoustic solver (not part of the public ABI).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace wave {
+
+// Stencil tile: TX x TY columns in the xy-plane, streamed along z. Each of the
+// 256 threads owns VX consecutive x points of one row and keeps a register
+// queue of 2r+1 z-planes; x/y neighbours come from an LDS copy of the plane.
+constexpr int TX = 64;
+constexpr int TY = 16;
+constexpr int VX = 4;
+constexpr int NTX = TX / VX;     // threads along x
+constexpr int NTHREADS = NTX * TY;
+constexpr int MAXR = 8;          // SO <= 16
+constexpr int SAMPLE_THREADS = 256;
+
+// Pitched field geometry: rows padded to a multiple of 32 floats (128 bytes);
+// padding columns hold zeros, also in the v^2 dt^2 array, so they stay zero.
+struct Geom {
+  int nx, ny, nz, pitch;
+  int64_t plane;    // pitch * ny
+  int64_t nfield;   // pitch * ny * nz (elements)
+};
+
+// One injection entry: a grid point inside a tile at plane z, with its local
+// index in the tile and a range of (trace index, weight) terms.
+struct InjEntry {
+  int z;        // plane
+  int local;    // (j - tile_y) * TX + (i - tile_x)
+  int csr_beg;  // terms [csr_beg, csr_end)
+  int csr_end;
+  int grp_end;  // first entry of the next plane group in this tile
+  int pad0, pad1, pad2;
+};
+
+struct StepArgs {
+  // fields (pitched)
+  const float* cur;   // level read with neighbours (u^n or lambda^{n+1})
+  const float* prev;  // level read at the point only (u^{n-1} / lambda^{n+2})
+  float* out;         // result; may alias prev
+  const float* c2;    // v^2 dt^2
+  const float* bx;    // dt gamma_x / 2 per x (pitch entries, zero padded)
+  const float* by;    // per y
+  const float* bz;    // per z
+  Geom g;
+  // tiling
+  int ntile_x, ntile_y, nchunk, zchunk;
+  int nstencil_blocks;
+  int xcd_remap;      // 1: contiguous tile ranges per XCD
+  // weights pre-scaled by h_a^-2; wc = w0 (hx^-2 + hy^-2 + hz^-2)
+  float wx[MAXR + 1], wy[MAXR + 1], wz[MAXR + 1];
+  float wc;
+  // fused injection into `out`: per-tile entry lists
+  const int* tile_beg;         // [ntiles + 1]
+  const InjEntry* ent;
+  const int* csr_idx;          // trace index
+  const float* csr_w;          // weight
+  const float* trace_row;      // samples of this step (indexed by csr_idx) or null
+  // fused sampling of `cur` (extra blocks after the stencil blocks)
+  const int* samp_idx;         // [nsamp][8] pitched element index
+  const float* samp_w;         // [nsamp][8]
+  int nsamp;
+  float* samp_out;             // row of nsamp outputs, or null for none
+  // fused gradient accumulation: grad += ufwd * c2 * (L_h cur + injection)
+  const float* ufwd;
+  float* grad;
+};
+
+// Launchers (wave_kernels.hip). All return hipGetLastError() after the launch.
+hipError_t launch_step(const StepArgs& a, int r, bool grad, hipStream_t s);
+hipError_t launch_sample(const float* field, const int* idx, const float* w, int n,
+                         float* out, hipStream_t s);
+// dst (pitched, zero padded) = src (dense) or zero when src is null
+hipError_t launch_pack(const float* src, float* dst, Geom g, hipStream_t s);
+// dst (dense) = src (pitched)
+hipError_t launch_unpack(const float* src, float* dst, Geom g, hipStream_t s);
+// c2 (pitched) = (float)(v^2 dt^2) computed in double
+hipError_t launch_prep_c2(const float* vel, float* c2, Geom g, double dt, hipStream_t s);
+// grad_vel (dense) = scale * graw / v^3
+hipError_t launch_grad_finalize(const float* graw, const float* vel, float* grad_vel, Geom g,
+                                double scale, hipStream_t s);
+// dst = src for n floats
+hipError_t launch_copy(const float* src, float* dst, int64_t n, hipStream_t s);
+
+}  // namespace wave

@@ -1,0 +1,380 @@
+// wave_kernels.hip -- gfx950 kernels of the acoustic leapfrog solver.
+//
+// One launch of step_kernel advances one time level of
+//   out = ( 2 cur - (1-b) prev + c2 (L_h cur + inj) ) / (1+b)
+// (the damped leapfrog update of the paper's SO2 listing, Section 2.1,
+// generalised to a star Laplacian of order 2r), fused with
+//   * point-source injection (inj: per-tile lists of grid points, each with its
+//     trilinear terms, summed in a fixed order and scattered through LDS),
+//   * sampling of `cur` at receiver points (extra workgroups after the stencil
+//     workgroups; `cur` is read-only during the step, so sampling the previous
+//     step's result here needs no extra launch),
+//   * optionally the gradient accumulation grad += ufwd * c2 (L_h cur + inj).
+//
+// Memory plan per step (FP32): read cur, prev, c2 and write out once each from
+// HBM -- 16 bytes per point; halo re-reads of cur are served by L2.
+#include "wave_internal.h"
+
+namespace wave {
+
+namespace {
+
+__device__ __forceinline__ float4 ld4(const float* p) {
+  return *reinterpret_cast<const float4*>(p);
+}
+__device__ __forceinline__ void st4(float* p, const float4& v) {
+  *reinterpret_cast<float4*>(p) = v;
+}
+__device__ __forceinline__ float comp(const float4& v, int i) {
+  return i == 0 ? v.x : i == 1 ? v.y : i == 2 ? v.z : v.w;
+}
+__device__ __forceinline__ void set_comp(float4& v, int i, float s) {
+  if (i == 0) v.x = s; else if (i == 1) v.y = s; else if (i == 2) v.z = s; else v.w = s;
+}
+
+// Weighted sum over up to 8 trilinear corners (unused corners carry weight 0
+// and index 0).
+__device__ __forceinline__ float sample_point(const float* f, const int* idx, const float* w,
+                                              int r) {
+  float acc = 0.f;
+#pragma unroll
+  for (int c = 0; c < 8; ++c) acc = fmaf(w[8 * r + c], f[idx[8 * r + c]], acc);
+  return acc;
+}
+
+// Block id -> logical tile id. Workgroups are dealt round-robin to the 8 XCDs;
+// remapping gives each XCD a contiguous run of logical tiles (whole xy-planes
+// of consecutive z-chunks), so tiles that exchange halos share one L2.
+__device__ __forceinline__ int remap_tile(int b, int nb) {
+  const int q = nb >> 3, rem = nb & 7;
+  const int xcd = b & 7, k = b >> 3;
+  const int base = xcd < rem ? xcd * (q + 1) : rem * (q + 1) + (xcd - rem) * q;
+  return base + k;
+}
+
+}  // namespace
+
+template <int R, bool GRAD>
+__global__ void __launch_bounds__(NTHREADS) step_kernel(const StepArgs a) {
+  constexpr int XH = R <= 4 ? 4 : 8;  // x-halo width in floats (multiple of 4)
+  constexpr int XH4 = XH / 4;
+  constexpr int LROW4 = NTX + 2 * XH4;  // float4 per LDS row
+  constexpr int LROWS = TY + 2 * R;
+  constexpr int NH = 2 * R * NTX + 2 * TY * XH4;  // halo float4 per plane
+  constexpr int NHP = (NH + NTHREADS - 1) / NTHREADS;
+  __shared__ float4 lds[2][LROWS * LROW4];
+  __shared__ float4 inj[TY * NTX];
+
+  const int bid = blockIdx.x;
+  if (bid >= a.nstencil_blocks) {
+    const int r = (bid - a.nstencil_blocks) * NTHREADS + threadIdx.x;
+    if (a.samp_out != nullptr && r < a.nsamp)
+      a.samp_out[r] = sample_point(a.cur, a.samp_idx, a.samp_w, r);
+    return;
+  }
+  const int t = a.xcd_remap ? remap_tile(bid, a.nstencil_blocks) : bid;
+  const int tx_t = t % a.ntile_x;
+  const int rest = t / a.ntile_x;
+  const int ty_t = rest % a.ntile_y;
+  const int zc = rest / a.ntile_y;
+  const int xt = tx_t * TX, yt = ty_t * TY;
+  const int nx = a.g.nx, ny = a.g.ny, nz = a.g.nz;
+  const int64_t plane = a.g.plane;
+  const int z0 = zc * a.zchunk;
+  const int z1 = min(z0 + a.zchunk, nz);
+  const int tid = threadIdx.x;
+  const int tx = tid % NTX, ty = tid / NTX;
+  const int x0 = xt + tx * VX, y = yt + ty;
+  const bool colok = (x0 < nx) && (y < ny);
+  const int col = y * a.g.pitch + x0;
+  const float4 zero4 = make_float4(0.f, 0.f, 0.f, 0.f);
+
+  // Halo items of this thread (fixed for the whole z sweep).
+  int hoff[NHP], hlds[NHP];
+  bool hok[NHP];
+#pragma unroll
+  for (int k = 0; k < NHP; ++k) {
+    const int i = tid + k * NTHREADS;
+    int gy = 0, gx = 0, row = 0, c4 = 0;
+    bool in = i < NH;
+    if (i < R * NTX) {
+      row = i / NTX; c4 = XH4 + i % NTX;
+      gy = yt - R + row; gx = xt + 4 * (i % NTX);
+    } else if (i < 2 * R * NTX) {
+      const int j = i - R * NTX;
+      row = R + TY + j / NTX; c4 = XH4 + j % NTX;
+      gy = yt + TY + j / NTX; gx = xt + 4 * (j % NTX);
+    } else if (i < 2 * R * NTX + TY * XH4) {
+      const int j = i - 2 * R * NTX;
+      row = R + j / XH4; c4 = j % XH4;
+      gy = yt + j / XH4; gx = xt - XH + 4 * (j % XH4);
+    } else {
+      const int j = i - 2 * R * NTX - TY * XH4;
+      row = R + j / XH4; c4 = XH4 + NTX + j % XH4;
+      gy = yt + j / XH4; gx = xt + TX + 4 * (j % XH4);
+    }
+    hlds[k] = in ? row * LROW4 + c4 : -1;
+    hok[k] = in && gy >= 0 && gy < ny && gx >= 0 && gx < nx;
+    hoff[k] = hok[k] ? gy * a.g.pitch + gx : 0;
+  }
+
+  // Sponge factors: b = bx[x] + by[y] + bz[z].
+  const float4 bxv = colok ? ld4(a.bx + x0) : zero4;
+  const float byv = y < ny ? a.by[y] : 0.f;
+
+  // Register queue of planes z-R .. z+R for this thread's four points.
+  float4 q[2 * R + 1];
+#pragma unroll
+  for (int s = 0; s <= 2 * R; ++s) {
+    const int z = z0 - R + s;
+    q[s] = (colok && z >= 0 && z < nz) ? ld4(a.cur + z * plane + col) : zero4;
+  }
+  {
+    float4 hv[NHP];
+#pragma unroll
+    for (int k = 0; k < NHP; ++k) hv[k] = hok[k] ? ld4(a.cur + z0 * plane + hoff[k]) : zero4;
+    lds[0][(ty + R) * LROW4 + XH4 + tx] = q[R];
+#pragma unroll
+    for (int k = 0; k < NHP; ++k)
+      if (hlds[k] >= 0) lds[0][hlds[k]] = hv[k];
+  }
+  inj[tid] = zero4;
+  float4 up = colok ? ld4(a.prev + z0 * plane + col) : zero4;
+  float4 cc = colok ? ld4(a.c2 + z0 * plane + col) : zero4;
+  __syncthreads();
+
+  int e = 0, e_end = 0;
+  if (a.tile_beg != nullptr) {
+    e = a.tile_beg[t];
+    e_end = a.tile_beg[t + 1];
+  }
+
+  for (int z = z0; z < z1; ++z) {
+    const int buf = (z - z0) & 1;
+    const bool more = z + 1 < z1;
+    // Prefetch for plane z+1.
+    float4 nq = zero4, nup = zero4, ncc = zero4;
+    float4 nhv[NHP];
+    {
+      const int zq = z + R + 1;
+      if (colok && more && zq < nz) nq = ld4(a.cur + zq * plane + col);
+#pragma unroll
+      for (int k = 0; k < NHP; ++k)
+        nhv[k] = (hok[k] && more) ? ld4(a.cur + (z + 1) * plane + hoff[k]) : zero4;
+      if (colok && more) {
+        nup = ld4(a.prev + (z + 1) * plane + col);
+        ncc = ld4(a.c2 + (z + 1) * plane + col);
+      }
+    }
+
+    // Laplacian of plane z.
+    const float4* L = lds[buf];
+    const int crow = (ty + R) * LROW4 + XH4 + tx;
+    float xv[4 + 2 * XH];  // x0-XH .. x0+3+XH
+#pragma unroll
+    for (int k = -XH4; k <= XH4; ++k) {
+      const float4 v = k == 0 ? q[R] : L[crow + k];
+      xv[XH + 4 * k + 0] = v.x; xv[XH + 4 * k + 1] = v.y;
+      xv[XH + 4 * k + 2] = v.z; xv[XH + 4 * k + 3] = v.w;
+    }
+    float lap[4];
+#pragma unroll
+    for (int p = 0; p < 4; ++p) lap[p] = a.wc * comp(q[R], p);
+#pragma unroll
+    for (int s = 1; s <= R; ++s) {
+      const float4 ym = L[crow - s * LROW4];
+      const float4 yp = L[crow + s * LROW4];
+#pragma unroll
+      for (int p = 0; p < 4; ++p) {
+        lap[p] = fmaf(a.wx[s], xv[XH + p - s] + xv[XH + p + s], lap[p]);
+        lap[p] = fmaf(a.wy[s], comp(ym, p) + comp(yp, p), lap[p]);
+        lap[p] = fmaf(a.wz[s], comp(q[R - s], p) + comp(q[R + s], p), lap[p]);
+      }
+    }
+
+    // Fused injection at this plane (uniform branch).
+    if (e < e_end && a.ent[e].z == z) {
+      const int ge = a.ent[e].grp_end;
+      for (int i = e + tid; i < ge; i += NTHREADS) {
+        const InjEntry en = a.ent[i];
+        float s = 0.f;
+        for (int c = en.csr_beg; c < en.csr_end; ++c)
+          s = fmaf(a.csr_w[c], a.trace_row[a.csr_idx[c]], s);
+        reinterpret_cast<float*>(inj)[en.local] = s;
+      }
+      __syncthreads();
+      const float4 iv = inj[tid];
+      lap[0] += iv.x; lap[1] += iv.y; lap[2] += iv.z; lap[3] += iv.w;
+      inj[tid] = zero4;
+      e = ge;
+    }
+
+    // Damped leapfrog update.
+    const float bzv = a.bz[z];
+    float4 o, src;
+#pragma unroll
+    for (int p = 0; p < 4; ++p) {
+      const float b = (comp(bxv, p) + byv) + bzv;
+      const float u = comp(q[R], p), um = comp(up, p);
+      const float cl = comp(cc, p) * lap[p];
+      set_comp(src, p, cl);
+      const float num = fmaf(b, um, 2.f * u - um) + cl;
+      set_comp(o, p, num * __builtin_amdgcn_rcpf(1.f + b));
+    }
+    if (colok) {
+      st4(a.out + z * plane + col, o);
+      if constexpr (GRAD) {
+        float4 gv = ld4(a.grad + z * plane + col);
+        const float4 uf = ld4(a.ufwd + z * plane + col);
+        gv.x = fmaf(uf.x, src.x, gv.x); gv.y = fmaf(uf.y, src.y, gv.y);
+        gv.z = fmaf(uf.z, src.z, gv.z); gv.w = fmaf(uf.w, src.w, gv.w);
+        st4(a.grad + z * plane + col, gv);
+      }
+    }
+
+    // Stage plane z+1 into the other LDS buffer.
+    if (more) {
+      lds[buf ^ 1][crow] = q[R + 1];
+#pragma unroll
+      for (int k = 0; k < NHP; ++k)
+        if (hlds[k] >= 0) lds[buf ^ 1][hlds[k]] = nhv[k];
+    }
+    __syncthreads();
+#pragma unroll
+    for (int s = 0; s < 2 * R; ++s) q[s] = q[s + 1];
+    q[2 * R] = nq;
+    up = nup;
+    cc = ncc;
+  }
+}
+
+__global__ void sample_kernel(const float* f, const int* idx, const float* w, int n, float* out) {
+  const int r = blockIdx.x * blockDim.x + threadIdx.x;
+  if (r < n) out[r] = sample_point(f, idx, w, r);
+}
+
+__global__ void pack_kernel(const float* src, float* dst, Geom g) {
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  for (int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; p < g.nfield; p += stride) {
+    const int i = (int)(p % g.pitch);
+    const int64_t row = p / g.pitch;  // k*ny + j
+    dst[p] = (src != nullptr && i < g.nx) ? src[row * g.nx + i] : 0.f;
+  }
+}
+
+__global__ void unpack_kernel(const float* src, float* dst, Geom g) {
+  const int64_t n = (int64_t)g.nx * g.ny * g.nz;
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  for (int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; p < n; p += stride) {
+    const int64_t row = p / g.nx;
+    const int i = (int)(p - row * g.nx);
+    dst[p] = src[row * g.pitch + i];
+  }
+}
+
+__global__ void prep_c2_kernel(const float* vel, float* c2, Geom g, double dt2) {
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  for (int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; p < g.nfield; p += stride) {
+    const int i = (int)(p % g.pitch);
+    const int64_t row = p / g.pitch;
+    float v = 0.f;
+    if (i < g.nx) {
+      const double vv = (double)vel[row * g.nx + i];
+      v = (float)(vv * vv * dt2);
+    }
+    c2[p] = v;
+  }
+}
+
+__global__ void grad_finalize_kernel(const float* graw, const float* vel, float* gv, Geom g,
+                                     double scale) {
+  const int64_t n = (int64_t)g.nx * g.ny * g.nz;
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  for (int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; p < n; p += stride) {
+    const int64_t row = p / g.nx;
+    const int i = (int)(p - row * g.nx);
+    const double v = (double)vel[p];
+    gv[p] = (float)(scale * (double)graw[row * g.pitch + i] / (v * v * v));
+  }
+}
+
+__global__ void copy_kernel(const float* src, float* dst, int64_t n) {
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  for (int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; p < n; p += stride)
+    dst[p] = src[p];
+}
+
+namespace {
+int elementwise_blocks(int64_t n) {
+  int64_t b = (n + 255) / 256;
+  if (b > 8192) b = 8192;
+  if (b < 1) b = 1;
+  return (int)b;
+}
+}  // namespace
+
+template <int R>
+static hipError_t launch_r(const StepArgs& a, bool grad, hipStream_t s) {
+  const int nsamp_blocks = a.samp_out != nullptr ? (a.nsamp + NTHREADS - 1) / NTHREADS : 0;
+  const dim3 grid(a.nstencil_blocks + nsamp_blocks), block(NTHREADS);
+  if (grad)
+    hipLaunchKernelGGL((step_kernel<R, true>), grid, block, 0, s, a);
+  else
+    hipLaunchKernelGGL((step_kernel<R, false>), grid, block, 0, s, a);
+  return hipGetLastError();
+}
+
+hipError_t launch_step(const StepArgs& a, int r, bool grad, hipStream_t s) {
+  switch (r) {
+    case 1: return launch_r<1>(a, grad, s);
+    case 2: return launch_r<2>(a, grad, s);
+    case 3: return launch_r<3>(a, grad, s);
+    case 4: return launch_r<4>(a, grad, s);
+    case 5: return launch_r<5>(a, grad, s);
+    case 6: return launch_r<6>(a, grad, s);
+    case 7: return launch_r<7>(a, grad, s);
+    case 8: return launch_r<8>(a, grad, s);
+    default: return hipErrorInvalidValue;
+  }
+}
+
+hipError_t launch_sample(const float* field, const int* idx, const float* w, int n, float* out,
+                         hipStream_t s) {
+  if (n <= 0) return hipSuccess;
+  hipLaunchKernelGGL(sample_kernel, dim3((n + 255) / 256), dim3(256), 0, s, field, idx, w, n,
+                     out);
+  return hipGetLastError();
+}
+
+hipError_t launch_pack(const float* src, float* dst, Geom g, hipStream_t s) {
+  hipLaunchKernelGGL(pack_kernel, dim3(elementwise_blocks(g.nfield)), dim3(256), 0, s, src, dst,
+                     g);
+  return hipGetLastError();
+}
+
+hipError_t launch_unpack(const float* src, float* dst, Geom g, hipStream_t s) {
+  hipLaunchKernelGGL(unpack_kernel, dim3(elementwise_blocks((int64_t)g.nx * g.ny * g.nz)),
+                     dim3(256), 0, s, src, dst, g);
+  return hipGetLastError();
+}
+
+hipError_t launch_prep_c2(const float* vel, float* c2, Geom g, double dt, hipStream_t s) {
+  hipLaunchKernelGGL(prep_c2_kernel, dim3(elementwise_blocks(g.nfield)), dim3(256), 0, s, vel, c2,
+                     g, dt * dt);
+  return hipGetLastError();
+}
+
+hipError_t launch_grad_finalize(const float* graw, const float* vel, float* grad_vel, Geom g,
+                                double scale, hipStream_t s) {
+  hipLaunchKernelGGL(grad_finalize_kernel, dim3(elementwise_blocks((int64_t)g.nx * g.ny * g.nz)),
+                     dim3(256), 0, s, graw, vel, grad_vel, g, scale);
+  return hipGetLastError();
+}
+
+hipError_t launch_copy(const float* src, float* dst, int64_t n, hipStream_t s) {
+  if (n <= 0) return hipSuccess;
+  hipLaunchKernelGGL(copy_kernel, dim3(elementwise_blocks(n)), dim3(256), 0, s, src, dst, n);
+  return hipGetLastError();
+}
+
+}  // namespace wave
