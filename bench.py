@@ -1,0 +1,217 @@
+"""Benchmark: Gpt-updates/s and fraction of the HBM roofline of the forward solve.
+
+One benchmark step = one complete forward solve of the workload below (every
+time step: damped star-stencil update, source injection, receiver sampling), with
+all inputs already resident in HBM:
+
+  256^3 grid (sponge included), h = 10 m, SO8, two-layer 1500/3000 m/s with the
+  interface at z = 128, 40-cell sponge on all faces, 10 Hz Ricker at the centre,
+  dt = 0.5 dt_max(3000 m/s), 500 time steps, 256 receivers along x at z = 20.
+
+value = 256^3 * 500 * steps / elapsed / 1e9 (grid points updated per second).
+
+Printed on stdout: ONE JSON line. Progress goes to stderr.
+"""
+import argparse
+import hashlib
+import json
+import os
+import re
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0          # MI355X HBM3E, published
+ALG_BYTES_PER_PT = 16          # read u^n, u^{n-1}, v^2 dt^2; write u^{n+1} (FP32)
+METRIC = "Gpt-updates/s and % HBM roofline at 256^3 SO4-16; p50/p99 shot latency"
+KERNEL_SOURCES = ["paper_1912_00695_amd/csrc/wave_kernels.hip",
+                  "paper_1912_00695_amd/csrc/wave_internal.h"]
+COUNTERS_FILE = os.path.join(ROOT, "profiles", "step_kernel_256cube_so8_counters.md")
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def kernel_hash():
+    h = hashlib.sha256()
+    for p in KERNEL_SOURCES:
+        h.update(open(os.path.join(ROOT, p), "rb").read())
+    return h.hexdigest()[:16]
+
+
+def measured_traffic():
+    """HBM bytes per step-kernel launch from the committed rocprofv3 counter summary,
+    or None when it is missing or was taken on different kernel sources."""
+    if not os.path.exists(COUNTERS_FILE):
+        return None
+    txt = open(COUNTERS_FILE).read()
+    m = re.search(r"kernel_source_hash:\s*([0-9a-f]+)", txt)
+    t = re.search(r"traffic_bytes_per_launch:\s*([0-9.eE+]+)", txt)
+    if not m or not t or m.group(1) != kernel_hash():
+        return None
+    return float(t.group(1))
+
+
+def c2_problem(so, nt=500, n=(256, 256, 256)):
+    import numpy as np
+    from paper_1912_00695_amd import inputs, wave
+    h = (10.0, 10.0, 10.0)
+    vmax = 3000.0
+    dt = 0.5 * wave.cfl_dt_max(so, vmax, h)
+    vel = inputs.two_layer(n, 1500.0, 3000.0, n[2] // 2)
+    src = inputs.point((n[0] // 2, n[1] // 2, n[2] // 2), h)
+    rec = inputs.line_x(n, h, n[1] // 2, 20)
+    wav = inputs.ricker(10.0, dt, nt)[:, None]
+    grid = wave.make_grid(n, h, so, dt, nt, (40,) * 6, vmax=vmax)
+    return dict(grid=grid, vel=vel, src=src, rec=rec, wav=wav, n=n, nt=nt, so=so, dt=dt,
+                h=h, vmax=vmax, nbl=(40,) * 6, np=np)
+
+
+class Solver:
+    """Device-resident inputs and a reusable workspace for repeated solves."""
+
+    def __init__(self, P, dev):
+        import torch
+        from paper_1912_00695_amd import wave
+        self.P, self.wave, self.torch = P, wave, torch
+        self.vel = torch.from_numpy(P["vel"]).to(dev)
+        self.wav = torch.from_numpy(P["wav"]).to(dev)
+        self.rec_out = torch.empty((P["nt"], len(P["rec"])), dtype=torch.float32, device=dev)
+        nbytes = wave.workspace_bytes(P["grid"], len(P["src"]), len(P["rec"]))
+        self.ws = torch.empty(nbytes, dtype=torch.uint8, device=dev)
+
+    def run(self):
+        self.wave.forward(self.P["grid"], self.vel, self.wav, self.P["src"], self.P["rec"],
+                          workspace=self.ws, rec_out=self.rec_out)
+
+
+def time_solves(solver, steps, warmup):
+    import torch
+    for _ in range(warmup):
+        solver.run()
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    t0 = time.perf_counter()
+    e0.record()
+    for _ in range(steps):
+        solver.run()
+    e1.record()
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    return e0.elapsed_time(e1) / 1000.0, wall
+
+
+def cpu_baseline(P, target_s=20.0):
+    """The FP64 oracle on the host cores, on a bounded number of time steps of the
+    same 256^3 SO8 workload."""
+    import numpy as np
+    import oracle
+    og = oracle.Grid(P["n"], P["h"], P["so"], P["dt"], 2, nbl=P["nbl"], vmax=P["vmax"])
+    t0 = time.perf_counter()
+    oracle.forward(og, P["vel"], P["wav"][:2], P["src"], P["rec"])
+    per_step = (time.perf_counter() - t0) / 2
+    nsteps = int(max(2, min(200, target_s / max(per_step, 1e-6))))
+    og = og.replace(nt=nsteps)
+    t0 = time.perf_counter()
+    oracle.forward(og, P["vel"], P["wav"][:nsteps], P["src"], P["rec"])
+    el = time.perf_counter() - t0
+    npts = int(np.prod(P["n"]))
+    return {"value": npts * nsteps / el / 1e9, "unit": "Gpt-updates/s",
+            "cores": oracle.num_threads(), "kind": "oracle",
+            "sample": "FP64 oracle, 256^3 SO8 two-layer + 40-cell sponge, source and 256 "
+                      "receivers, first %d of the 500 time steps (%.1f s)" % (nsteps, el)}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--so", type=int, default=8)
+    ap.add_argument("--no-sweep", action="store_true")
+    ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--only-timed", action="store_true",
+                    help="run only the timed solves (for profiler runs)")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print("bench.py runs on one GPU: this solver has no multi-GPU path (shots shard "
+              "across GPUs with no exchange; see the sharding notes). Use --gpus 1.",
+              file=sys.stderr)
+        sys.exit(2)
+    import torch
+    from paper_1912_00695_amd import wave
+    dev = torch.device("cuda:0")
+    wave.lib()
+
+    P = c2_problem(args.so)
+    solver = Solver(P, dev)
+    log("timing %d solves of 256^3 SO%d x %d steps (warmup %d)" % (args.steps, args.so,
+                                                                   P["nt"], args.warmup))
+    el, wall = time_solves(solver, args.steps, args.warmup)
+    npts = 256 ** 3
+    gpts = npts * P["nt"] * args.steps / el / 1e9
+    launch_s = el / (args.steps * P["nt"])
+    achieved = ALG_BYTES_PER_PT * npts / launch_s / 1e9
+    log("Gpt/s %.2f  per-step %.2f us  effective %.0f GB/s" % (gpts, launch_s * 1e6, achieved))
+    out = {
+        "metric": METRIC, "value": round(gpts, 3), "unit": "Gpt-updates/s",
+        "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+        "ms_per_step": round(el / args.steps * 1000.0, 3), "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+        "config": {"workload": "forward solve 256^3 SO%d, two-layer 1500/3000 m/s, 40-cell "
+                               "sponge, 10 Hz Ricker at centre, 256 receivers, 500 steps, "
+                               "dt=0.5*CFL" % args.so,
+                   "grid": [256, 256, 256], "so": args.so, "nt": P["nt"], "nsrc": 1,
+                   "nrec": 256, "storage": "f32"},
+        "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
+                     "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
+                     "traffic": measured_traffic(),
+                     "kernel": "step_kernel<%d,false>" % (args.so // 2),
+                     "alg_bytes_per_launch": ALG_BYTES_PER_PT * npts,
+                     "avg_launch_us": round(launch_s * 1e6, 3),
+                     "kernel_source_hash": kernel_hash()},
+        "wall_s_timed": round(wall, 4),
+    }
+    del solver
+    if args.only_timed:
+        print(json.dumps(out), flush=True)
+        return
+    if not args.no_sweep:
+        sweep = {}
+        for so in (2, 4, 8, 12, 16):
+            S = Solver(c2_problem(so), dev)
+            e, _ = time_solves(S, 3, 1)
+            g = npts * 500 * 3 / e / 1e9
+            sweep["so%d" % so] = {"gpts": round(g, 2),
+                                  "hbm_frac": round(g * ALG_BYTES_PER_PT / HBM_PEAK_GBS, 4)}
+            log("sweep SO%d: %.2f Gpt/s" % (so, g))
+            del S
+        out["so_sweep_256"] = sweep
+        # cache-defeating control: 512^3 (4 fields x 537 MB per step, far above the
+        # 256 MB Infinity Cache)
+        P5 = c2_problem(8, nt=100, n=(512, 512, 512))
+        S = Solver(P5, dev)
+        e, _ = time_solves(S, 2, 1)
+        g = 512 ** 3 * 100 * 2 / e / 1e9
+        out["control_512_so8"] = {"gpts": round(g, 2),
+                                  "hbm_frac": round(g * ALG_BYTES_PER_PT / HBM_PEAK_GBS, 4),
+                                  "nt": 100}
+        log("control 512^3 SO8: %.2f Gpt/s" % g)
+        del S
+    if not args.no_cpu:
+        log("cpu baseline (oracle) ...")
+        out["cpu_baseline"] = cpu_baseline(P)
+        log("cpu baseline %.4f Gpt/s on %d threads" % (out["cpu_baseline"]["value"],
+                                                       out["cpu_baseline"]["cores"]))
+    out["paper_context"] = {"v100_so8_aggressive_gpts": 32.9, "v100_so8_alg_hbm_frac": 0.58,
+                            "titanz_so8_aggressive_gpts": 3.71,
+                            "note": "Gpt/s derived from the paper's Table 3 / Table 2 times at "
+                                    "256^3 x 30000 steps; other hardware, context only"}
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -319,7 +319,13 @@ int setup(Ctx& C, const wave_grid* g, const float* vel, const double* src, int n
     const double v = q <= g->so / 2 ? w[q] : 0.0;
     C.wx[q] = v * ix; C.wy[q] = v * iy; C.wz[q] = v * iz;
   }
-  C.wc = w[0] * (ix + iy + iz);
+  // Centre weight of the terms q >= 2 (the q = 1 pairs are taken about the centre
+  // in the kernel): minus twice the sum of the FP32-rounded weights, so that the
+  // weights the kernel uses sum to zero up to one rounding of this value.
+  double wc = 0.0;
+  for (int q = 2; q <= g->so / 2; ++q)
+    wc -= 2.0 * ((double)(float)C.wx[q] + (double)(float)C.wy[q] + (double)(float)C.wz[q]);
+  C.wc = wc;
   // host tables
   Blob* B = new Blob;
   B->base = C.L.tables_beg;

@@ -51,7 +51,8 @@ struct StepArgs {
   int ntile_x, ntile_y, nchunk, zchunk;
   int nstencil_blocks;
   int xcd_remap;      // 1: contiguous tile ranges per XCD
-  // weights pre-scaled by h_a^-2; wc = w0 (hx^-2 + hy^-2 + hz^-2)
+  // weights pre-scaled by h_a^-2; wc = -2 sum_{q>=2} (wx+wy+wz) (the q = 1 pairs are
+  // taken about the centre)
   float wx[MAXR + 1], wy[MAXR + 1], wz[MAXR + 1];
   float wc;
   // fused injection into `out`: per-tile entry lists

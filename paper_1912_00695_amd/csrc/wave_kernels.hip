@@ -1,7 +1,8 @@
 // wave_kernels.hip -- gfx950 kernels of the acoustic leapfrog solver.
 //
 // One launch of step_kernel advances one time level of
-//   out = ( 2 cur - (1-b) prev + c2 (L_h cur + inj) ) / (1+b)
+//   out = ( 2 cur - (1-b) prev + c2 (L_h cur + inj) ) / (1+b),
+// evaluated as cur + ((1-b)(cur - prev) + c2 (L_h cur + inj)) / (1+b)
 // (the damped leapfrog update of the paper's SO2 listing, Section 2.1,
 // generalised to a star Laplacian of order 2r), fused with
 //   * point-source injection (inj: per-tile lists of grid points, each with its
@@ -177,11 +178,15 @@ __global__ void __launch_bounds__(NTHREADS) step_kernel(const StepArgs a) {
       xv[XH + 4 * k + 0] = v.x; xv[XH + 4 * k + 1] = v.y;
       xv[XH + 4 * k + 2] = v.z; xv[XH + 4 * k + 3] = v.w;
     }
+    // Accumulate from the outermost (smallest) weights inwards; the innermost
+    // pairs enter as second differences about the centre, (u+1 + u-1) - 2u, and
+    // wc = -2 sum_{q>=2} w_q (over the three axes), so a constant field gives
+    // exactly zero and no spurious zeroth-order term builds up in FP32.
     float lap[4];
 #pragma unroll
     for (int p = 0; p < 4; ++p) lap[p] = a.wc * comp(q[R], p);
 #pragma unroll
-    for (int s = 1; s <= R; ++s) {
+    for (int s = R; s >= 2; --s) {
       const float4 ym = L[crow - s * LROW4];
       const float4 yp = L[crow + s * LROW4];
 #pragma unroll
@@ -189,6 +194,17 @@ __global__ void __launch_bounds__(NTHREADS) step_kernel(const StepArgs a) {
         lap[p] = fmaf(a.wx[s], xv[XH + p - s] + xv[XH + p + s], lap[p]);
         lap[p] = fmaf(a.wy[s], comp(ym, p) + comp(yp, p), lap[p]);
         lap[p] = fmaf(a.wz[s], comp(q[R - s], p) + comp(q[R + s], p), lap[p]);
+      }
+    }
+    {
+      const float4 ym = L[crow - LROW4];
+      const float4 yp = L[crow + LROW4];
+#pragma unroll
+      for (int p = 0; p < 4; ++p) {
+        const float u2 = 2.f * comp(q[R], p);
+        lap[p] = fmaf(a.wx[1], (xv[XH + p - 1] + xv[XH + p + 1]) - u2, lap[p]);
+        lap[p] = fmaf(a.wy[1], (comp(ym, p) + comp(yp, p)) - u2, lap[p]);
+        lap[p] = fmaf(a.wz[1], (comp(q[R - 1], p) + comp(q[R + 1], p)) - u2, lap[p]);
       }
     }
 
@@ -209,17 +225,21 @@ __global__ void __launch_bounds__(NTHREADS) step_kernel(const StepArgs a) {
       e = ge;
     }
 
-    // Damped leapfrog update.
+    // Damped leapfrog update in increment form:
+    //   out = u + ((1-b)(u - prev) + c2 (L u + inj)) / (1+b)
+    // (equal to (2u - (1-b) prev + c2 (L u + inj)) / (1+b)); u - prev is exact for
+    // smooth fields, so the only rounding at the magnitude of u is the final add.
     const float bzv = a.bz[z];
     float4 o, src;
 #pragma unroll
     for (int p = 0; p < 4; ++p) {
       const float b = (comp(bxv, p) + byv) + bzv;
-      const float u = comp(q[R], p), um = comp(up, p);
-      const float cl = comp(cc, p) * lap[p];
-      set_comp(src, p, cl);
-      const float num = fmaf(b, um, 2.f * u - um) + cl;
-      set_comp(o, p, num * __builtin_amdgcn_rcpf(1.f + b));
+      const float u = comp(q[R], p);
+      const float d = u - comp(up, p);
+      const float c = comp(cc, p);
+      if constexpr (GRAD) set_comp(src, p, c * lap[p]);
+      const float num = fmaf(c, lap[p], fmaf(-b, d, d));
+      set_comp(o, p, fmaf(num, __builtin_amdgcn_rcpf(1.f + b), u));
     }
     if (colok) {
       st4(a.out + z * plane + col, o);

@@ -87,28 +87,48 @@ def test_c2_full_size_so8_short():
     assert e_u <= TOL and e_r <= TOL
 
 
+@pytest.mark.parametrize("so", [4, 8, 16])
+def test_c2_full_length(so):
+    """The full benchmark problem (256^3, 500 steps, launch configuration of the
+    benchmark) against the oracle; a second receiver line near the source gives
+    the traces signal (the configured line at z = 20 is beyond the distance the
+    wave travels in 500 steps)."""
+    from paper_1912_00695_amd import inputs
+    case = c2_case(so, nt=500)
+    case.rec = np.concatenate([case.rec, inputs.line_x(case.n, case.h, 128, 150)])
+    print("case C2 256^3 SO%d nt=500" % so, flush=True)
+    g = _run(case)
+    rec, uf, _ = case.oracle_forward()
+    e_u, e_r = rel_l2(g["u_final"], uf), rel_l2(g["rec"], rec)
+    print("SO", so, "field", e_u, "traces", e_r, flush=True)
+    assert e_u <= TOL and e_r <= TOL
+
+
 def test_c2_full_size_properties():
-    """At the full benchmark size and length (256^3, SO8, 500 steps): the solve is
-    linear in the wavelet (scaling by 2 is exact in FP32, so bitwise), and swapping
-    an on-grid source and receiver gives the same trace (reciprocity)."""
-    import torch
+    """At the full benchmark size and length (256^3, SO8, 500 steps): linearity in
+    the wavelet and source-receiver reciprocity, to FP32 roundoff. (Scaling by 2 is
+    exact only until the first subnormal rounding differs; after that the two runs'
+    rounding errors decorrelate, so the comparison measures roundoff, not bits.)"""
+    from paper_1912_00695_amd import inputs
     case = c2_case(8, nt=500)
+    case.rec = np.concatenate([case.rec, inputs.line_x(case.n, case.h, 128, 150)])
     print("case C2 256^3 SO8 nt=500 linearity", flush=True)
     a = _run(case, want_final=False)["rec"]
     case.wavelet = 2.0 * case.wavelet
     b = _run(case, want_final=False)["rec"]
-    assert np.array_equal(b, 2.0 * a)
+    print("linearity rel", rel_l2(b, 2.0 * a), flush=True)
     assert np.abs(a).max() > 0
+    assert rel_l2(b, 2.0 * a) <= TOL
     case.wavelet = case.wavelet / 2.0
     A = np.array([[1280.0, 1280.0, 1280.0]])
-    B = np.array([[900.0, 1400.0, 200.0]])
+    B = np.array([[900.0, 1400.0, 1100.0]])
     case.src, case.rec = A, B
     ab = _run(case, want_final=False)["rec"]
     case.src, case.rec = B, A
     ba = _run(case, want_final=False)["rec"]
-    print("reciprocity rel", rel_l2(ab, ba), flush=True)
+    print("reciprocity rel", rel_l2(ab, ba), "max", np.abs(ab).max(), flush=True)
+    assert np.abs(ab).max() > 1e-6
     assert rel_l2(ab, ba) <= TOL
-    torch.cuda.synchronize()
 
 
 def test_edge_cases():
@@ -122,16 +142,21 @@ def test_edge_cases():
     assert np.array_equal(g["u_final"], case.u0)
     assert g["rec"].shape == (0, len(case.rec))
     # degenerate thin grids (single plane / single row / single column)
+    from helpers import Case
+    from paper_1912_00695_amd import inputs
     for n in [(1, 1, 40), (40, 1, 1), (1, 30, 1), (5, 3, 2), (64, 16, 1)]:
-        case = ragged_case(4, nt=12, n=n)
-        case.nbl = (0,) * 6
-        case.src = np.array([[0.0, 0.0, 0.0]])
-        case.wavelet = case.wavelet[:, :1]
-        case.rec = np.array([[0.0, 0.0, 0.0], [(n[0] - 1) * case.h[0], (n[1] - 1) * case.h[1],
-                                               (n[2] - 1) * case.h[2]]])
-        _oracle_inputs(case)
-        g = _run(case)
-        rec, uf, _ = case.oracle_forward()
+        h = (10.0, 12.0, 9.0)
+        vel = inputs.smooth_random_range(n, 1500.0, 2600.0, 6.0, seed=1)
+        c = Case(n, h, 4, 12, vel, 2600.0)
+        c.src = np.array([[0.0, 0.0, 0.0]])
+        c.wavelet = inputs.random_field((12, 1), 5)
+        c.rec = np.array([[0.0, 0.0, 0.0], [(n[0] - 1) * h[0], (n[1] - 1) * h[1],
+                                            (n[2] - 1) * h[2]]])
+        c.u0 = inputs.random_field(vel.shape, 6) * 1e-2
+        c.um1 = inputs.random_field(vel.shape, 7) * 1e-2
+        g = _run(c)
+        rec, uf, _ = c.oracle_forward()
+        print("thin grid", n, rel_l2(g["u_final"], uf), rel_l2(g["rec"], rec), flush=True)
         assert rel_l2(g["u_final"], uf) <= TOL and rel_l2(g["rec"], rec) <= TOL, n
     # the workspace is reusable: same call twice on one workspace, identical bits
     case = ragged_case(8, nt=20)
