@@ -135,6 +135,9 @@ def main():
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--only-timed", action="store_true",
                     help="run only the timed solves (for profiler runs)")
+    ap.add_argument("--with-copy", action="store_true",
+                    help="after the timed solves, run a plain 256 MiB device copy three times "
+                         "(calibrates profiler byte counters against a known size)")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py runs on one GPU: this solver has no multi-GPU path (shots shard "
@@ -176,6 +179,14 @@ def main():
         "wall_s_timed": round(wall, 4),
     }
     del solver
+    if args.with_copy:
+        x = torch.ones(64 * 1024 * 1024, dtype=torch.float32, device=dev)
+        y = torch.empty_like(x)
+        for _ in range(3):
+            y.copy_(x)
+        torch.cuda.synchronize()
+        out["copy_calibration_bytes"] = 2 * x.numel() * 4
+        del x, y
     if args.only_timed:
         print(json.dumps(out), flush=True)
         return
