@@ -104,6 +104,54 @@ def time_solves(solver, steps, warmup):
     return e0.elapsed_time(e1) / 1000.0, wall
 
 
+def reduced_precision_leg(dev):
+    """512^3 SO8, smoothed-random 1500-4500 m/s, 15 Hz Ricker at the centre, 1000 steps,
+    40-cell sponge: throughput of each wavefield storage format, speedup over FP32
+    storage and rel-L2 of the final field and traces against the FP32 run."""
+    import numpy as np
+    import torch
+    from paper_1912_00695_amd import inputs, wave
+    n, h, nt = (512, 512, 512), (10.0, 10.0, 10.0), 1000
+    vmax = 4500.0
+    dt = 0.5 * wave.cfl_dt_max(8, vmax, h)
+    vel = torch.from_numpy(inputs.smooth_random_range(n, 1500.0, 4500.0, 20.0, seed=4)).to(dev)
+    wav = torch.from_numpy(inputs.ricker(15.0, dt, nt)[:, None]).to(dev)
+    src = inputs.point((256, 256, 256), h)
+    rec = np.concatenate([inputs.line_x(n, h, 256, 266), inputs.line_x(n, h, 256, 20)])
+    res, ref = {}, None
+    for name, st in (("f32", 0), ("f16_diff", 17), ("bf16_diff", 18), ("f16", 1), ("bf16", 2)):
+        g = wave.make_grid(n, h, 8, dt, nt, (40,) * 6, vmax=vmax, storage=st)
+        ws = torch.empty(wave.workspace_bytes(g, 1, len(rec)), dtype=torch.uint8, device=dev)
+        recb = torch.empty((nt, len(rec)), dtype=torch.float32, device=dev)
+        wave.forward(g, vel, wav, src, rec, workspace=ws, rec_out=recb)
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        wave.forward(g, vel, wav, src, rec, workspace=ws, rec_out=recb)
+        e1.record()
+        torch.cuda.synchronize()
+        el = e0.elapsed_time(e1) / 1000.0
+        out = wave.forward(g, vel, wav, src, rec, workspace=ws, want_final=True)
+        u = out["u_final"].double()
+        r = out["rec"].double()
+        gp = 512 ** 3 * nt / el / 1e9
+        bpp = {0: 16, 1: 10, 2: 10, 17: 12, 18: 12}[st]
+        item = {"gpts": round(gp, 2), "alg_bytes_per_pt": bpp,
+                "hbm_frac": round(gp * bpp / HBM_PEAK_GBS, 4)}
+        if ref is None:
+            ref = (u, r, gp)
+        else:
+            item["speedup_vs_f32"] = round(gp / ref[2], 3)
+            item["field_rel_l2_vs_f32"] = float(torch.linalg.norm(u - ref[0]) /
+                                                torch.linalg.norm(ref[0]))
+            item["traces_rel_l2_vs_f32"] = float(torch.linalg.norm(r - ref[1]) /
+                                                 torch.linalg.norm(ref[1]))
+        res[name] = item
+        log("lowp %s: %s" % (name, item))
+        del ws, out, u, r, recb
+    return res
+
+
 def cpu_baseline(P, target_s=20.0):
     """The FP64 oracle on the host cores, on a bounded number of time steps of the
     same 256^3 SO8 workload."""
@@ -212,6 +260,8 @@ def main():
                                   "nt": 100}
         log("control 512^3 SO8: %.2f Gpt/s" % g)
         del S
+    if not args.no_sweep:
+        out["lowp_512_so8"] = reduced_precision_leg(dev)
     if not args.no_cpu:
         log("cpu baseline (oracle) ...")
         out["cpu_baseline"] = cpu_baseline(P)

@@ -60,10 +60,16 @@ extern "C" {
 #define WAVE_EBUSY (-5)   /* serving engine: request exceeds the memory budget              */
 #define WAVE_EAGAIN (-6)  /* serving engine: result not ready yet                           */
 
-/* Wavefield storage formats (arithmetic is FP32 in every format). */
+/* Wavefield storage formats (arithmetic is FP32 in every format). The 16-bit
+ * formats store each level as value * 2^e with a power-of-two scale e chosen per
+ * level on the device from the previous level's maximum (with headroom), and
+ * apply only to wave_forward. WAVE_STORE_DIFF (or-ed onto F16 / BF16) stores
+ * u^n and the difference u^n - u^{n-1} instead of u^n and u^{n-1}: 12 instead
+ * of 10 bytes moved per point and step, much smaller rounding error. */
 #define WAVE_STORE_F32 0
 #define WAVE_STORE_F16 1
 #define WAVE_STORE_BF16 2
+#define WAVE_STORE_DIFF 16
 
 /* Workspace modes for wave_workspace_bytes(). */
 #define WAVE_MODE_FORWARD 0
@@ -79,7 +85,8 @@ typedef struct {
   int32_t nbl[6];      /* sponge width per face: x-, x+, y-, y+, z-, z+ (0 = none)    */
   double vmax;         /* velocity bound [m/s]: max(vel) <= vmax is the caller's
                           promise; sets the sponge strength and the dt check         */
-  int32_t storage;     /* WAVE_STORE_*                                                */
+  int32_t storage;     /* WAVE_STORE_F32 | WAVE_STORE_F16 | WAVE_STORE_BF16, the last two
+                          optionally | WAVE_STORE_DIFF                               */
 } wave_grid;
 
 /* Largest stable dt of the leapfrog scheme (von Neumann):
@@ -110,6 +117,10 @@ size_t wave_checkpoint_bytes(const wave_grid* g, int ckpt_every);
  *   u_final   optional [nz][ny][nx] receives u^{nt}
  *   ckpt      optional checkpoint buffer (wave_checkpoint_bytes) receiving
  *             (u^{kC}, u^{kC-1}) for k = 0..ceil(nt/C)-1, C = ckpt_every
+ *             (FP32 storage only)
+ * With 16-bit storage the levels are rounded to the storage format after every
+ * step (the error against FP32 storage is a property of the format; the FP32
+ * arithmetic is unchanged).
  * Returns WAVE_OK or a negative status. */
 int wave_forward(const wave_grid* g, const float* vel, const float* wavelet,
                  const double* src_xyz_h, int nsrc, const double* rec_xyz_h, int nrec,
@@ -121,7 +132,7 @@ int wave_forward(const wave_grid* g, const float* vel, const float* wavelet,
  * wavelet to receiver data (zero initial state). Runs
  *   lambda^n = (2 l^{n+1} - (1-b) l^{n+2} + dt^2 v^2 (L_h l^{n+1} + R^T d^n)) / (1+b)
  * for n = nt-1..0 from lambda^{nt} = lambda^{nt+1} = 0 and samples
- * src_out^n = P lambda^n.
+ * src_out^n = P lambda^n. FP32 storage only.
  *   rec_data  [nt][nrec] (device), src_out [nt][nsrc] (device, may be NULL
  *   when nsrc == 0), lam_final optional [nz][ny][nx] receives lambda^0. */
 int wave_adjoint(const wave_grid* g, const float* vel, const float* rec_data,
@@ -139,7 +150,7 @@ int wave_adjoint(const wave_grid* g, const float* vel, const float* rec_data,
  * Forward levels come from ckpt (filled by wave_forward with the same
  * ckpt_every) or, when ckpt is NULL, from an internal forward pass that keeps
  * checkpoints in the workspace; each segment of ckpt_every steps is recomputed
- * before its adjoint steps. */
+ * before its adjoint steps. FP32 storage only. */
 int wave_gradient(const wave_grid* g, const float* vel, const float* wavelet,
                   const double* src_xyz_h, int nsrc, const double* rec_xyz_h, int nrec,
                   const float* rec_grad, const float* ckpt, int ckpt_every,

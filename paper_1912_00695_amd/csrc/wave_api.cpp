@@ -50,7 +50,9 @@ bool grid_ok(const wave_grid* g) {
     if (g->nbl[2 * a] < 0 || g->nbl[2 * a + 1] < 0) return false;
     if (g->nbl[2 * a] + g->nbl[2 * a + 1] > n[a]) return false;
   }
-  if (g->storage != WAVE_STORE_F32) return false;
+  const int st = g->storage & ~WAVE_STORE_DIFF;
+  if (st != WAVE_STORE_F32 && st != WAVE_STORE_F16 && st != WAVE_STORE_BF16) return false;
+  if (st == WAVE_STORE_F32 && (g->storage & WAVE_STORE_DIFF)) return false;
   const int64_t pitch = (g->nx + 31) / 32 * 32;
   if (pitch * g->ny * (int64_t)g->nz >= ((int64_t)1 << 31)) return false;
   return true;
@@ -108,8 +110,11 @@ struct PointTables {   // offsets into the workspace
   size_t tile_beg, ent, csr_idx, csr_w, samp_idx, samp_w;
 };
 
+int store_kind(const wave_grid* g) { return g->storage & ~WAVE_STORE_DIFF; }
+bool store_diff(const wave_grid* g) { return (g->storage & WAVE_STORE_DIFF) != 0; }
+
 struct Layout {
-  size_t c2, bx, by, bz, u[2];
+  size_t c2, bx, by, bz, u[2], d, meta;
   PointTables pts[2];  // 0: sources, 1: receivers
   size_t tables_beg, tables_end;
   size_t graw, lam[2], seg, ick;  // gradient mode
@@ -123,9 +128,12 @@ Layout make_layout(const wave_grid* g, int nsrc, int nrec, int mode, int ckpt_ev
   size_t off = 0;
   auto take = [&](size_t bytes) { size_t o = off; off = align_up(off + bytes); return o; };
   const size_t fbytes = (size_t)G.nfield * sizeof(float);
+  const size_t ubytes = (size_t)G.nfield * (store_kind(g) == WAVE_STORE_F32 ? 4 : 2);
   L.c2 = take(fbytes);
-  L.u[0] = take(fbytes);
-  L.u[1] = take(fbytes);
+  L.u[0] = take(ubytes);
+  L.u[1] = take(ubytes);
+  L.d = store_diff(g) ? take(ubytes) : 0;
+  L.meta = store_kind(g) != WAVE_STORE_F32 ? take((size_t)5 * (g->nt + 3) * sizeof(unsigned)) : 0;
   L.tables_beg = off;
   L.bx = take((size_t)G.pitch * sizeof(float));
   L.by = take((size_t)G.ny * sizeof(float));
@@ -352,8 +360,22 @@ int setup(Ctx& C, const wave_grid* g, const float* vel, const double* src, int n
   return WAVE_OK;
 }
 
+LevelMeta level_meta(const Ctx& C) {
+  LevelMeta m{};
+  if (C.L.meta == 0) return m;
+  const int64_t L = C.g->nt + 3;
+  unsigned* base = C.at<unsigned>(C.L.meta);
+  m.mu = base;
+  m.md = base + L;
+  m.injb = reinterpret_cast<float*>(base + 2 * L);
+  m.eu = reinterpret_cast<int*>(base + 3 * L);
+  m.ed = reinterpret_cast<int*>(base + 4 * L);
+  return m;
+}
+
 StepArgs base_args(const Ctx& C) {
   StepArgs a{};
+  a.meta = level_meta(C);
   a.c2 = C.at<float>(C.L.c2);
   a.bx = C.at<float>(C.L.bx);
   a.by = C.at<float>(C.L.by);
@@ -398,6 +420,48 @@ void set_samp(StepArgs& a, const Ctx& C, int set, int np, float* row) {
   } else {
     a.samp_idx = nullptr; a.samp_w = nullptr; a.nsamp = 0; a.samp_out = nullptr;
   }
+}
+
+// Forward solve with 16-bit wavefield storage (FP32 arithmetic). Naive form:
+// levels u^n, u^{n-1}; difference form: u^n and d^n = u^n - u^{n-1}.
+int forward_reduced(Ctx& C, const float* wavelet, int nsrc, int nrec, float* rec_out,
+                    const float* u0, const float* um1, float* u_final) {
+  const wave_grid* g = C.g;
+  const int stk = store_kind(g) == WAVE_STORE_F16 ? ST_F16 : ST_BF16;
+  const bool diff = store_diff(g);
+  const LevelMeta meta = level_meta(C);
+  void* U[2] = {C.ws + C.L.u[0], C.ws + C.L.u[1]};
+  void* D = diff ? C.ws + C.L.d : nullptr;
+  HIP_TRY(launch_zero_words(meta.mu, (int64_t)5 * (g->nt + 3), C.s));
+  const float c2max = (float)(g->vmax * g->vmax * g->dt * g->dt);
+  if (nsrc > 0) HIP_TRY(launch_inj_bound(wavelet, g->nt, nsrc, c2max, meta.injb, C.s));
+  HIP_TRY(launch_encode_initial(u0, um1, U[0], diff ? D : U[1], stk, diff, meta, 0, C.G, C.s));
+  StepArgs a = base_args(C);
+  const int r = g->so / 2;
+  for (int n = 0; n < g->nt; ++n) {
+    a.level = n;
+    a.cur = U[n & 1];
+    if (diff) {
+      a.prev = D;
+      a.out = D;
+      a.out_u = U[(n + 1) & 1];
+    } else {
+      a.prev = U[(n + 1) & 1];
+      a.out = U[(n + 1) & 1];
+      a.out_u = nullptr;
+    }
+    set_inj(a, C, 0, nsrc, nsrc > 0 ? wavelet + (int64_t)n * nsrc : nullptr);
+    set_samp(a, C, 1, nrec, n >= 1 && nrec > 0 ? rec_out + (int64_t)(n - 1) * nrec : nullptr);
+    HIP_TRY(launch_step(a, r, false, stk, diff, C.s));
+  }
+  if (nrec > 0 && g->nt > 0) {
+    const PointTables& P = C.L.pts[1];
+    HIP_TRY(launch_sample(U[g->nt & 1], stk, meta, g->nt, C.at<int>(P.samp_idx),
+                          C.at<float>(P.samp_w), nrec, rec_out + (int64_t)(g->nt - 1) * nrec,
+                          C.s));
+  }
+  if (u_final != nullptr) HIP_TRY(launch_decode(U[g->nt & 1], stk, meta, g->nt, u_final, C.G, C.s));
+  return WAVE_OK;
 }
 
 int validate(const wave_grid* g) {
@@ -464,10 +528,13 @@ int wave_forward(const wave_grid* g, const float* vel, const float* wavelet,
   if (nrec > 0 && rec_out == nullptr && g->nt > 0) return WAVE_EINVAL;
   if (!points_ok(g, src_xyz_h, nsrc) || !points_ok(g, rec_xyz_h, nrec)) return WAVE_EINVAL;
   if (ckpt != nullptr && ckpt_every <= 0) return WAVE_EINVAL;
+  if (ckpt != nullptr && store_kind(g) != WAVE_STORE_F32) return WAVE_EINVAL;
   Ctx C;
   st = setup(C, g, vel, src_xyz_h, nsrc, rec_xyz_h, nrec, WAVE_MODE_FORWARD, 0, workspace,
              ws_bytes, hip_stream);
   if (st) return st;
+  if (store_kind(g) != WAVE_STORE_F32)
+    return forward_reduced(C, wavelet, nsrc, nrec, rec_out, u0, um1, u_final);
   float* X[2] = {C.at<float>(C.L.u[0]), C.at<float>(C.L.u[1])};
   HIP_TRY(launch_pack(u0, X[0], C.G, C.s));
   HIP_TRY(launch_pack(um1, X[1], C.G, C.s));
@@ -487,12 +554,13 @@ int wave_forward(const wave_grid* g, const float* vel, const float* wavelet,
     a.out = prev;
     set_inj(a, C, 0, nsrc, nsrc > 0 ? wavelet + (int64_t)n * nsrc : nullptr);
     set_samp(a, C, 1, nrec, n >= 1 && nrec > 0 ? rec_out + (int64_t)(n - 1) * nrec : nullptr);
-    HIP_TRY(launch_step(a, r, false, C.s));
+    HIP_TRY(launch_step(a, r, false, ST_F32, false, C.s));
   }
   if (nrec > 0 && g->nt > 0) {
     const PointTables& P = C.L.pts[1];
-    HIP_TRY(launch_sample(X[g->nt & 1], C.at<int>(P.samp_idx), C.at<float>(P.samp_w), nrec,
-                          rec_out + (int64_t)(g->nt - 1) * nrec, C.s));
+    HIP_TRY(launch_sample(X[g->nt & 1], ST_F32, LevelMeta{}, g->nt, C.at<int>(P.samp_idx),
+                          C.at<float>(P.samp_w), nrec, rec_out + (int64_t)(g->nt - 1) * nrec,
+                          C.s));
   }
   if (u_final != nullptr) HIP_TRY(launch_unpack(X[g->nt & 1], u_final, C.G, C.s));
   return WAVE_OK;
@@ -505,6 +573,7 @@ int wave_adjoint(const wave_grid* g, const float* vel, const float* rec_data,
   int st = validate(g);
   if (st) return st;
   if (vel == nullptr || nsrc < 0 || nrec < 0) return WAVE_EINVAL;
+  if (g->storage != WAVE_STORE_F32) return WAVE_EINVAL;
   if (nrec > 0 && rec_data == nullptr && g->nt > 0) return WAVE_EINVAL;
   if (nsrc > 0 && src_out == nullptr && g->nt > 0) return WAVE_EINVAL;
   if (!points_ok(g, src_xyz_h, nsrc) || !points_ok(g, rec_xyz_h, nrec)) return WAVE_EINVAL;
@@ -525,12 +594,12 @@ int wave_adjoint(const wave_grid* g, const float* vel, const float* rec_data,
     set_inj(a, C, 1, nrec, nrec > 0 ? rec_data + (int64_t)n * nrec : nullptr);
     set_samp(a, C, 0, nsrc,
              (n + 1 <= nt - 1 && nsrc > 0) ? src_out + (int64_t)(n + 1) * nsrc : nullptr);
-    HIP_TRY(launch_step(a, r, false, C.s));
+    HIP_TRY(launch_step(a, r, false, ST_F32, false, C.s));
   }
   if (nsrc > 0 && nt > 0) {
     const PointTables& P = C.L.pts[0];
-    HIP_TRY(launch_sample(X[0], C.at<int>(P.samp_idx), C.at<float>(P.samp_w), nsrc, src_out,
-                          C.s));
+    HIP_TRY(launch_sample(X[0], ST_F32, LevelMeta{}, 0, C.at<int>(P.samp_idx),
+                          C.at<float>(P.samp_w), nsrc, src_out, C.s));
   }
   if (lam_final != nullptr) HIP_TRY(launch_unpack(X[0], lam_final, C.G, C.s));
   return WAVE_OK;
@@ -543,6 +612,7 @@ int wave_gradient(const wave_grid* g, const float* vel, const float* wavelet,
   int st = validate(g);
   if (st) return st;
   if (vel == nullptr || grad_vel == nullptr || nsrc < 0 || nrec < 0) return WAVE_EINVAL;
+  if (g->storage != WAVE_STORE_F32) return WAVE_EINVAL;
   if (nsrc > 0 && wavelet == nullptr && g->nt > 0) return WAVE_EINVAL;
   if (nrec > 0 && rec_grad == nullptr && g->nt > 0) return WAVE_EINVAL;
   if (ckpt != nullptr && ckpt_every <= 0) return WAVE_EINVAL;
@@ -577,7 +647,7 @@ int wave_gradient(const wave_grid* g, const float* vel, const float* wavelet,
       }
       a.cur = cur; a.prev = prev; a.out = prev;
       set_inj(a, C, 0, nsrc, nsrc > 0 ? wavelet + (int64_t)n * nsrc : nullptr);
-      HIP_TRY(launch_step(a, r, false, C.s));
+      HIP_TRY(launch_step(a, r, false, ST_F32, false, C.s));
     }
   }
   for (int s = C.L.nseg - 1; s >= 0; --s) {
@@ -598,7 +668,7 @@ int wave_gradient(const wave_grid* g, const float* vel, const float* wavelet,
       a.prev = seg + (int64_t)(n - n0) * F;
       a.out = seg + (int64_t)(n - n0 + 2) * F;
       set_inj(a, C, 0, nsrc, nsrc > 0 ? wavelet + (int64_t)n * nsrc : nullptr);
-      HIP_TRY(launch_step(a, r, false, C.s));
+      HIP_TRY(launch_step(a, r, false, ST_F32, false, C.s));
     }
     for (int n = n1 - 1; n >= n0; --n) {
       a.cur = lam[(n + 1) & 1];
@@ -611,13 +681,13 @@ int wave_gradient(const wave_grid* g, const float* vel, const float* wavelet,
                (grad_wavelet != nullptr && nsrc > 0 && n + 1 <= nt - 1)
                    ? grad_wavelet + (int64_t)(n + 1) * nsrc
                    : nullptr);
-      HIP_TRY(launch_step(a, r, true, C.s));
+      HIP_TRY(launch_step(a, r, true, ST_F32, false, C.s));
     }
   }
   if (grad_wavelet != nullptr && nsrc > 0 && nt > 0) {
     const PointTables& P = C.L.pts[0];
-    HIP_TRY(launch_sample(lam[0], C.at<int>(P.samp_idx), C.at<float>(P.samp_w), nsrc,
-                          grad_wavelet, C.s));
+    HIP_TRY(launch_sample(lam[0], ST_F32, LevelMeta{}, 0, C.at<int>(P.samp_idx),
+                          C.at<float>(P.samp_w), nsrc, grad_wavelet, C.s));
   }
   // dL/dm = -graw / dt^2  ->  dL/dv = -2 v^-3 dL/dm = (2 / dt^2) graw / v^3
   HIP_TRY(launch_grad_finalize(graw, vel, grad_vel, C.G, 2.0 / (g->dt * g->dt), C.s));

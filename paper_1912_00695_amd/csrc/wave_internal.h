@@ -37,12 +37,32 @@ struct InjEntry {
   int pad0, pad1, pad2;
 };
 
+// Storage formats of the wavefield levels (arithmetic is FP32 in all of them).
+enum StoreKind { ST_F32 = 0, ST_F16 = 1, ST_BF16 = 2 };
+
+// Reduced-precision levels are stored as value * 2^e (e an integer chosen per level
+// so that the level's bound maps below 2^kScaleTarget). Per-level bookkeeping in
+// device memory, L = nt + 3 entries each, level m at index m + 1:
+//   mu[m+1], md[m+1]  bits of max|u^m| and max|u^m - u^{m-1}| (atomicMax of the
+//                     non-negative float bits written while encoding level m)
+//   injb[n]           bound on the injected increment of step n
+//   eu[m+1], ed[m+1]  scale exponents of level m's u and difference arrays
+constexpr int kScaleTarget = 12;
+struct LevelMeta {
+  unsigned* mu;
+  unsigned* md;
+  float* injb;
+  int* eu;
+  int* ed;
+};
+
 struct StepArgs {
-  // fields (pitched)
-  const float* cur;   // level read with neighbours (u^n or lambda^{n+1})
-  const float* prev;  // level read at the point only (u^{n-1} / lambda^{n+2})
-  float* out;         // result; may alias prev
-  const float* c2;    // v^2 dt^2
+  // fields (pitched); element type given by the storage kind
+  const void* cur;    // level read with neighbours (u^n or lambda^{n+1})
+  const void* prev;   // read at the point only: u^{n-1} (or the difference u^n - u^{n-1})
+  void* out;          // result written in place of prev (u^{n+1}, or the new difference)
+  void* out_u;        // difference form only: u^{n+1} (the other u buffer)
+  const float* c2;    // v^2 dt^2 (FP32)
   const float* bx;    // dt gamma_x / 2 per x (pitch entries, zero padded)
   const float* by;    // per y
   const float* bz;    // per z
@@ -69,12 +89,17 @@ struct StepArgs {
   // fused gradient accumulation: grad += ufwd * c2 * (L_h cur + injection)
   const float* ufwd;
   float* grad;
+  // reduced-precision storage: level index n of `cur`, and the bookkeeping
+  int level;
+  LevelMeta meta;
 };
 
 // Launchers (wave_kernels.hip). All return hipGetLastError() after the launch.
-hipError_t launch_step(const StepArgs& a, int r, bool grad, hipStream_t s);
-hipError_t launch_sample(const float* field, const int* idx, const float* w, int n,
-                         float* out, hipStream_t s);
+// st: StoreKind; diff: difference-form storage (reduced precision only).
+hipError_t launch_step(const StepArgs& a, int r, bool grad, int st, bool diff, hipStream_t s);
+// out[i] = sum_c w[8i+c] field[idx[8i+c]], the field decoded with level m's scale
+hipError_t launch_sample(const void* field, int st, LevelMeta meta, int m, const int* idx,
+                         const float* w, int n, float* out, hipStream_t s);
 // dst (pitched, zero padded) = src (dense) or zero when src is null
 hipError_t launch_pack(const float* src, float* dst, Geom g, hipStream_t s);
 // dst (dense) = src (pitched)
@@ -86,5 +111,18 @@ hipError_t launch_grad_finalize(const float* graw, const float* vel, float* grad
                                 double scale, hipStream_t s);
 // dst = src for n floats
 hipError_t launch_copy(const float* src, float* dst, int64_t n, hipStream_t s);
+// reduced precision: zero n words
+hipError_t launch_zero_words(unsigned* p, int64_t n, hipStream_t s);
+// injb[k] = c2max * 8 * max_j |trace[k][j]| for k < nt (bound of one step's injection)
+hipError_t launch_inj_bound(const float* trace, int nt, int ntr, float c2max, float* injb,
+                            hipStream_t s);
+// initial levels (dense FP32, null = zero): record max|a| (and max|a - b| when
+// diff) for level m, choose its scales, then encode a (and a - b, or b as level
+// m - 1 in the naive form) into the pitched stores
+hipError_t launch_encode_initial(const float* a, const float* b, void* ua, void* ub, int st,
+                                 bool diff, LevelMeta meta, int m, Geom g, hipStream_t s);
+// dst (dense FP32) = decoded level m of src (pitched, storage st)
+hipError_t launch_decode(const void* src, int st, LevelMeta meta, int m, float* dst, Geom g,
+                         hipStream_t s);
 
 }  // namespace wave

@@ -13,7 +13,9 @@
 //   * optionally the gradient accumulation grad += ufwd * c2 (L_h cur + inj).
 //
 // Memory plan per step (FP32): read cur, prev, c2 and write out once each from
-// HBM -- 16 bytes per point; halo re-reads of cur are served by L2.
+// HBM -- 16 bytes per point; halo re-reads of cur are served by L2. With 16-bit
+// wavefield storage (FP16 / BF16, FP32 arithmetic) the naive form moves
+// 2+2+4+2 = 10 bytes per point and the difference form (u, u - u_prev) 12.
 #include "wave_internal.h"
 
 namespace wave {
@@ -33,15 +35,6 @@ __device__ __forceinline__ void set_comp(float4& v, int i, float s) {
   if (i == 0) v.x = s; else if (i == 1) v.y = s; else if (i == 2) v.z = s; else v.w = s;
 }
 
-// Weighted sum over up to 8 trilinear corners (unused corners carry weight 0
-// and index 0).
-__device__ __forceinline__ float sample_point(const float* f, const int* idx, const float* w,
-                                              int r) {
-  float acc = 0.f;
-#pragma unroll
-  for (int c = 0; c < 8; ++c) acc = fmaf(w[8 * r + c], f[idx[8 * r + c]], acc);
-  return acc;
-}
 
 // Block id -> logical tile id. Workgroups are dealt round-robin to the 8 XCDs;
 // remapping gives each XCD a contiguous run of logical tiles (whole xy-planes
@@ -53,9 +46,91 @@ __device__ __forceinline__ int remap_tile(int b, int nb) {
   return base + k;
 }
 
+
+// Wavefield element access per storage kind: 4 consecutive values (16-byte or
+// 8-byte aligned) or 1 value, widened to / narrowed from FP32 (round to nearest
+// even).
+template <int ST> struct Store;
+template <> struct Store<ST_F32> {
+  __device__ static float4 ld(const void* b, int64_t i) {
+    return ld4(static_cast<const float*>(b) + i);
+  }
+  __device__ static float ld1(const void* b, int64_t i) { return static_cast<const float*>(b)[i]; }
+  __device__ static void st(void* b, int64_t i, const float4& v) {
+    st4(static_cast<float*>(b) + i, v);
+  }
+};
+typedef _Float16 h4v __attribute__((ext_vector_type(4)));
+template <> struct Store<ST_F16> {
+  __device__ static float4 ld(const void* b, int64_t i) {
+    const h4v h = *reinterpret_cast<const h4v*>(static_cast<const _Float16*>(b) + i);
+    return make_float4((float)h.x, (float)h.y, (float)h.z, (float)h.w);
+  }
+  __device__ static float ld1(const void* b, int64_t i) {
+    return (float)static_cast<const _Float16*>(b)[i];
+  }
+  __device__ static void st(void* b, int64_t i, const float4& v) {
+    h4v h;
+    h.x = (_Float16)v.x; h.y = (_Float16)v.y; h.z = (_Float16)v.z; h.w = (_Float16)v.w;
+    *reinterpret_cast<h4v*>(static_cast<_Float16*>(b) + i) = h;
+  }
+};
+__device__ __forceinline__ unsigned bf16_rne(float f) {
+  const unsigned u = __float_as_uint(f);
+  return (u + 0x7fffu + ((u >> 16) & 1u)) >> 16;
+}
+template <> struct Store<ST_BF16> {
+  __device__ static float4 ld(const void* b, int64_t i) {
+    const uint2 r = *reinterpret_cast<const uint2*>(static_cast<const unsigned short*>(b) + i);
+    return make_float4(__uint_as_float(r.x << 16), __uint_as_float(r.x & 0xffff0000u),
+                       __uint_as_float(r.y << 16), __uint_as_float(r.y & 0xffff0000u));
+  }
+  __device__ static float ld1(const void* b, int64_t i) {
+    return __uint_as_float((unsigned)static_cast<const unsigned short*>(b)[i] << 16);
+  }
+  __device__ static void st(void* b, int64_t i, const float4& v) {
+    uint2 r;
+    r.x = bf16_rne(v.x) | (bf16_rne(v.y) << 16);
+    r.y = bf16_rne(v.z) | (bf16_rne(v.w) << 16);
+    *reinterpret_cast<uint2*>(static_cast<unsigned short*>(b) + i) = r;
+  }
+};
+
+__device__ __forceinline__ float4 mul4(const float4& v, float s) {
+  return make_float4(v.x * s, v.y * s, v.z * s, v.w * s);
+}
+
+// Scale exponent e for a level whose magnitudes are bounded by b: b * 2^e stays
+// below 2^kScaleTarget (16x below the FP16 maximum).
+__device__ __forceinline__ int scale_exp(float b) {
+  int e = -126;
+  if (b > 0.f && b <= 3.0e38f) {
+    int ex;
+    frexpf(b, &ex);  // b < 2^ex
+    e = ex;
+  }
+  return min(max(kScaleTarget - e, -120), 120);
+}
+
+__device__ __forceinline__ float wave_max(float v) {
+#pragma unroll
+  for (int o = 32; o >= 1; o >>= 1) v = fmaxf(v, __shfl_xor(v, o, 64));
+  return v;
+}
+
+// Weighted sum over up to 8 trilinear corners (unused corners carry weight 0
+// and index 0) of a stored level, decoded with factor dec.
+template <int ST>
+__device__ __forceinline__ float sample_point(const void* f, float dec, const int* idx,
+                                              const float* w, int r) {
+  float acc = 0.f;
+#pragma unroll
+  for (int c = 0; c < 8; ++c) acc = fmaf(w[8 * r + c], Store<ST>::ld1(f, idx[8 * r + c]) * dec, acc);
+  return acc;
+}
 }  // namespace
 
-template <int R, bool GRAD>
+template <int R, bool GRAD, int ST, bool DIFF>
 __global__ void __launch_bounds__(NTHREADS) step_kernel(const StepArgs a) {
   constexpr int XH = R <= 4 ? 4 : 8;  // x-halo width in floats (multiple of 4)
   constexpr int XH4 = XH / 4;
@@ -66,11 +141,37 @@ __global__ void __launch_bounds__(NTHREADS) step_kernel(const StepArgs a) {
   __shared__ float4 lds[2][LROWS * LROW4];
   __shared__ float4 inj[TY * NTX];
 
+  // Per-level scales of reduced-precision storage: decode cur and prev, choose
+  // the encode scales of the level written here from the previous maxima.
+  float dec_c = 1.f, dec_p = 1.f, enc_u = 1.f, enc_d = 1.f;
+  if constexpr (ST != ST_F32) {
+    const int n = a.level;
+    dec_c = ldexpf(1.f, -a.meta.eu[n + 1]);
+    dec_p = ldexpf(1.f, DIFF ? -a.meta.ed[n + 1] : -a.meta.eu[n]);
+    const float mun = __uint_as_float(a.meta.mu[n + 1]);
+    const float injb = a.meta.injb[n];
+    int eu, ed = 0;
+    if constexpr (DIFF) {
+      // |d^{n+1}| <= |d^n| + c2 |L u^n| + inj, c2 |L| <= 4 under the CFL limit
+      const float bd = __uint_as_float(a.meta.md[n + 1]) + 4.f * mun + injb;
+      ed = scale_exp(bd);
+      eu = scale_exp(mun + bd);
+    } else {
+      eu = scale_exp(8.f * fmaxf(mun, __uint_as_float(a.meta.mu[n])) + injb);
+    }
+    enc_u = ldexpf(1.f, eu);
+    enc_d = ldexpf(1.f, ed);
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
+      a.meta.eu[n + 2] = eu;
+      if (DIFF) a.meta.ed[n + 2] = ed;
+    }
+  }
+
   const int bid = blockIdx.x;
   if (bid >= a.nstencil_blocks) {
     const int r = (bid - a.nstencil_blocks) * NTHREADS + threadIdx.x;
     if (a.samp_out != nullptr && r < a.nsamp)
-      a.samp_out[r] = sample_point(a.cur, a.samp_idx, a.samp_w, r);
+      a.samp_out[r] = sample_point<ST>(a.cur, dec_c, a.samp_idx, a.samp_w, r);
     return;
   }
   const int t = a.xcd_remap ? remap_tile(bid, a.nstencil_blocks) : bid;
@@ -89,6 +190,15 @@ __global__ void __launch_bounds__(NTHREADS) step_kernel(const StepArgs a) {
   const bool colok = (x0 < nx) && (y < ny);
   const int col = y * a.g.pitch + x0;
   const float4 zero4 = make_float4(0.f, 0.f, 0.f, 0.f);
+  auto ldc = [&](int64_t i) {
+    const float4 v = Store<ST>::ld(a.cur, i);
+    if constexpr (ST == ST_F32) return v; else return mul4(v, dec_c);
+  };
+  auto ldp = [&](int64_t i) {
+    const float4 v = Store<ST>::ld(a.prev, i);
+    if constexpr (ST == ST_F32) return v; else return mul4(v, dec_p);
+  };
+  float mx_u = 0.f, mx_d = 0.f;  // running maxima of the written level (reduced precision)
 
   // Halo items of this thread (fixed for the whole z sweep).
   int hoff[NHP], hlds[NHP];
@@ -128,19 +238,19 @@ __global__ void __launch_bounds__(NTHREADS) step_kernel(const StepArgs a) {
 #pragma unroll
   for (int s = 0; s <= 2 * R; ++s) {
     const int z = z0 - R + s;
-    q[s] = (colok && z >= 0 && z < nz) ? ld4(a.cur + z * plane + col) : zero4;
+    q[s] = (colok && z >= 0 && z < nz) ? ldc(z * plane + col) : zero4;
   }
   {
     float4 hv[NHP];
 #pragma unroll
-    for (int k = 0; k < NHP; ++k) hv[k] = hok[k] ? ld4(a.cur + z0 * plane + hoff[k]) : zero4;
+    for (int k = 0; k < NHP; ++k) hv[k] = hok[k] ? ldc(z0 * plane + hoff[k]) : zero4;
     lds[0][(ty + R) * LROW4 + XH4 + tx] = q[R];
 #pragma unroll
     for (int k = 0; k < NHP; ++k)
       if (hlds[k] >= 0) lds[0][hlds[k]] = hv[k];
   }
   inj[tid] = zero4;
-  float4 up = colok ? ld4(a.prev + z0 * plane + col) : zero4;
+  float4 up = colok ? ldp(z0 * plane + col) : zero4;
   float4 cc = colok ? ld4(a.c2 + z0 * plane + col) : zero4;
   __syncthreads();
 
@@ -158,12 +268,12 @@ __global__ void __launch_bounds__(NTHREADS) step_kernel(const StepArgs a) {
     float4 nhv[NHP];
     {
       const int zq = z + R + 1;
-      if (colok && more && zq < nz) nq = ld4(a.cur + zq * plane + col);
+      if (colok && more && zq < nz) nq = ldc(zq * plane + col);
 #pragma unroll
       for (int k = 0; k < NHP; ++k)
-        nhv[k] = (hok[k] && more) ? ld4(a.cur + (z + 1) * plane + hoff[k]) : zero4;
+        nhv[k] = (hok[k] && more) ? ldc((z + 1) * plane + hoff[k]) : zero4;
       if (colok && more) {
-        nup = ld4(a.prev + (z + 1) * plane + col);
+        nup = ldp((z + 1) * plane + col);
         ncc = ld4(a.c2 + (z + 1) * plane + col);
       }
     }
@@ -229,26 +339,48 @@ __global__ void __launch_bounds__(NTHREADS) step_kernel(const StepArgs a) {
     //   out = u + ((1-b)(u - prev) + c2 (L u + inj)) / (1+b)
     // (equal to (2u - (1-b) prev + c2 (L u + inj)) / (1+b)); u - prev is exact for
     // smooth fields, so the only rounding at the magnitude of u is the final add.
+    // In the difference form prev already holds d = u^n - u^{n-1} and the new
+    // difference is stored beside u^{n+1}.
     const float bzv = a.bz[z];
-    float4 o, src;
+    float4 o, dn, src;
 #pragma unroll
     for (int p = 0; p < 4; ++p) {
       const float b = (comp(bxv, p) + byv) + bzv;
       const float u = comp(q[R], p);
-      const float d = u - comp(up, p);
+      const float d = DIFF ? comp(up, p) : u - comp(up, p);
       const float c = comp(cc, p);
       if constexpr (GRAD) set_comp(src, p, c * lap[p]);
       const float num = fmaf(c, lap[p], fmaf(-b, d, d));
-      set_comp(o, p, fmaf(num, __builtin_amdgcn_rcpf(1.f + b), u));
+      const float inv = __builtin_amdgcn_rcpf(1.f + b);
+      if constexpr (DIFF) {
+        const float dd = num * inv;
+        set_comp(dn, p, dd);
+        set_comp(o, p, u + dd);
+      } else {
+        set_comp(o, p, fmaf(num, inv, u));
+      }
     }
     if (colok) {
-      st4(a.out + z * plane + col, o);
+      const int64_t at = z * plane + col;
+      if constexpr (ST == ST_F32) {
+        Store<ST>::st(a.out, at, o);
+      } else {
+        mx_u = fmaxf(mx_u, fmaxf(fmaxf(fabsf(o.x), fabsf(o.y)), fmaxf(fabsf(o.z), fabsf(o.w))));
+        if constexpr (DIFF) {
+          mx_d = fmaxf(mx_d, fmaxf(fmaxf(fabsf(dn.x), fabsf(dn.y)), fmaxf(fabsf(dn.z), fabsf(dn.w))));
+          Store<ST>::st(a.out_u, at, mul4(o, enc_u));
+          Store<ST>::st(a.out, at, mul4(dn, enc_d));
+        } else {
+          Store<ST>::st(a.out, at, mul4(o, enc_u));
+        }
+      }
       if constexpr (GRAD) {
-        float4 gv = ld4(a.grad + z * plane + col);
-        const float4 uf = ld4(a.ufwd + z * plane + col);
+        float* gp = a.grad + at;
+        float4 gv = ld4(gp);
+        const float4 uf = ld4(a.ufwd + at);
         gv.x = fmaf(uf.x, src.x, gv.x); gv.y = fmaf(uf.y, src.y, gv.y);
         gv.z = fmaf(uf.z, src.z, gv.z); gv.w = fmaf(uf.w, src.w, gv.w);
-        st4(a.grad + z * plane + col, gv);
+        st4(gp, gv);
       }
     }
 
@@ -266,11 +398,24 @@ __global__ void __launch_bounds__(NTHREADS) step_kernel(const StepArgs a) {
     up = nup;
     cc = ncc;
   }
+  if constexpr (ST != ST_F32) {
+    // maxima of the level just written, for the next step's scale choice
+    mx_u = wave_max(mx_u);
+    if (DIFF) mx_d = wave_max(mx_d);
+    if ((threadIdx.x & 63) == 0) {
+      atomicMax(a.meta.mu + a.level + 2, __float_as_uint(mx_u));
+      if (DIFF) atomicMax(a.meta.md + a.level + 2, __float_as_uint(mx_d));
+    }
+  }
 }
 
-__global__ void sample_kernel(const float* f, const int* idx, const float* w, int n, float* out) {
+template <int ST>
+__global__ void sample_kernel(const void* f, LevelMeta meta, int m, const int* idx,
+                              const float* w, int n, float* out) {
+  float dec = 1.f;
+  if constexpr (ST != ST_F32) dec = ldexpf(1.f, -meta.eu[m + 1]);
   const int r = blockIdx.x * blockDim.x + threadIdx.x;
-  if (r < n) out[r] = sample_point(f, idx, w, r);
+  if (r < n) out[r] = sample_point<ST>(f, dec, idx, w, r);
 }
 
 __global__ void pack_kernel(const float* src, float* dst, Geom g) {
@@ -324,6 +469,103 @@ __global__ void copy_kernel(const float* src, float* dst, int64_t n) {
     dst[p] = src[p];
 }
 
+__global__ void zero_words_kernel(unsigned* p, int64_t n) {
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride) p[i] = 0u;
+}
+
+// One block per time step: injb[k] = c2max * 8 * max_j |trace[k][j]| (a point gets
+// trilinear contributions from at most 8 traces, weights <= 1).
+__global__ void inj_bound_kernel(const float* trace, int ntr, float c2max, float* injb) {
+  __shared__ float red[256];
+  const int k = blockIdx.x;
+  float m = 0.f;
+  for (int j = threadIdx.x; j < ntr; j += blockDim.x)
+    m = fmaxf(m, fabsf(trace[(int64_t)k * ntr + j]));
+  red[threadIdx.x] = m;
+  __syncthreads();
+  for (int o = 128; o >= 1; o >>= 1) {
+    if ((int)threadIdx.x < o) red[threadIdx.x] = fmaxf(red[threadIdx.x], red[threadIdx.x + o]);
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) injb[k] = c2max * 8.f * red[0];
+}
+
+// Maxima of initial levels: slot_a <- max|a|, slot_b <- max|a - b| (diff) or max|b|.
+__global__ void initial_max_kernel(const float* a, const float* b, bool diff, unsigned* slot_a,
+                                   unsigned* slot_b, int64_t n) {
+  __shared__ float ra[256], rb[256];
+  float ma = 0.f, mb = 0.f;
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  for (int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; p < n; p += stride) {
+    const float va = a != nullptr ? a[p] : 0.f, vb = b != nullptr ? b[p] : 0.f;
+    ma = fmaxf(ma, fabsf(va));
+    mb = fmaxf(mb, fabsf(diff ? va - vb : vb));
+  }
+  ra[threadIdx.x] = ma;
+  rb[threadIdx.x] = mb;
+  __syncthreads();
+  for (int o = 128; o >= 1; o >>= 1) {
+    if ((int)threadIdx.x < o) {
+      ra[threadIdx.x] = fmaxf(ra[threadIdx.x], ra[threadIdx.x + o]);
+      rb[threadIdx.x] = fmaxf(rb[threadIdx.x], rb[threadIdx.x + o]);
+    }
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) {
+    atomicMax(slot_a, __float_as_uint(ra[0]));
+    atomicMax(slot_b, __float_as_uint(rb[0]));
+  }
+}
+
+// Scale exponents of the initial levels (one thread).
+__global__ void initial_scales_kernel(LevelMeta meta, int m, bool diff) {
+  if (threadIdx.x != 0 || blockIdx.x != 0) return;
+  meta.eu[m + 1] = scale_exp(__uint_as_float(meta.mu[m + 1]));
+  if (diff)
+    meta.ed[m + 1] = scale_exp(__uint_as_float(meta.md[m + 1]));
+  else
+    meta.eu[m] = scale_exp(__uint_as_float(meta.mu[m]));
+}
+
+// Encode initial levels into pitched stores (padding columns zero).
+template <int ST>
+__global__ void encode_initial_kernel(const float* a, const float* b, void* ua, void* ub,
+                                      bool diff, LevelMeta meta, int m, Geom g) {
+  const float ea = ldexpf(1.f, meta.eu[m + 1]);
+  const float eb = ldexpf(1.f, diff ? meta.ed[m + 1] : meta.eu[m]);
+  const int64_t n4 = g.nfield / 4;
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  for (int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; q < n4; q += stride) {
+    const int64_t p = 4 * q;
+    const int i = (int)(p % g.pitch);
+    const int64_t row = p / g.pitch;
+    float va[4], vb[4];
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+      const bool in = i + k < g.nx;
+      const float x = (in && a != nullptr) ? a[row * g.nx + i + k] : 0.f;
+      const float y = (in && b != nullptr) ? b[row * g.nx + i + k] : 0.f;
+      va[k] = x;
+      vb[k] = diff ? x - y : y;
+    }
+    Store<ST>::st(ua, p, make_float4(va[0] * ea, va[1] * ea, va[2] * ea, va[3] * ea));
+    Store<ST>::st(ub, p, make_float4(vb[0] * eb, vb[1] * eb, vb[2] * eb, vb[3] * eb));
+  }
+}
+
+template <int ST>
+__global__ void decode_kernel(const void* src, LevelMeta meta, int m, float* dst, Geom g) {
+  const float dec = ldexpf(1.f, -meta.eu[m + 1]);
+  const int64_t n = (int64_t)g.nx * g.ny * g.nz;
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  for (int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; p < n; p += stride) {
+    const int64_t row = p / g.nx;
+    const int i = (int)(p - row * g.nx);
+    dst[p] = Store<ST>::ld1(src, row * g.pitch + i) * dec;
+  }
+}
+
 namespace {
 int elementwise_blocks(int64_t n) {
   int64_t b = (n + 255) / 256;
@@ -331,38 +573,54 @@ int elementwise_blocks(int64_t n) {
   if (b < 1) b = 1;
   return (int)b;
 }
-}  // namespace
 
-template <int R>
-static hipError_t launch_r(const StepArgs& a, bool grad, hipStream_t s) {
+template <int R, bool GRAD, int ST, bool DIFF>
+hipError_t launch_r(const StepArgs& a, hipStream_t s) {
   const int nsamp_blocks = a.samp_out != nullptr ? (a.nsamp + NTHREADS - 1) / NTHREADS : 0;
   const dim3 grid(a.nstencil_blocks + nsamp_blocks), block(NTHREADS);
-  if (grad)
-    hipLaunchKernelGGL((step_kernel<R, true>), grid, block, 0, s, a);
-  else
-    hipLaunchKernelGGL((step_kernel<R, false>), grid, block, 0, s, a);
+  hipLaunchKernelGGL((step_kernel<R, GRAD, ST, DIFF>), grid, block, 0, s, a);
   return hipGetLastError();
 }
 
-hipError_t launch_step(const StepArgs& a, int r, bool grad, hipStream_t s) {
+template <int R>
+hipError_t launch_variant(const StepArgs& a, bool grad, int st, bool diff, hipStream_t s) {
+  if (st == ST_F32) {
+    if (diff) return hipErrorInvalidValue;
+    return grad ? launch_r<R, true, ST_F32, false>(a, s) : launch_r<R, false, ST_F32, false>(a, s);
+  }
+  if (grad) return hipErrorInvalidValue;
+  if (st == ST_F16)
+    return diff ? launch_r<R, false, ST_F16, true>(a, s) : launch_r<R, false, ST_F16, false>(a, s);
+  if (st == ST_BF16)
+    return diff ? launch_r<R, false, ST_BF16, true>(a, s) : launch_r<R, false, ST_BF16, false>(a, s);
+  return hipErrorInvalidValue;
+}
+}  // namespace
+
+hipError_t launch_step(const StepArgs& a, int r, bool grad, int st, bool diff, hipStream_t s) {
   switch (r) {
-    case 1: return launch_r<1>(a, grad, s);
-    case 2: return launch_r<2>(a, grad, s);
-    case 3: return launch_r<3>(a, grad, s);
-    case 4: return launch_r<4>(a, grad, s);
-    case 5: return launch_r<5>(a, grad, s);
-    case 6: return launch_r<6>(a, grad, s);
-    case 7: return launch_r<7>(a, grad, s);
-    case 8: return launch_r<8>(a, grad, s);
+    case 1: return launch_variant<1>(a, grad, st, diff, s);
+    case 2: return launch_variant<2>(a, grad, st, diff, s);
+    case 3: return launch_variant<3>(a, grad, st, diff, s);
+    case 4: return launch_variant<4>(a, grad, st, diff, s);
+    case 5: return launch_variant<5>(a, grad, st, diff, s);
+    case 6: return launch_variant<6>(a, grad, st, diff, s);
+    case 7: return launch_variant<7>(a, grad, st, diff, s);
+    case 8: return launch_variant<8>(a, grad, st, diff, s);
     default: return hipErrorInvalidValue;
   }
 }
 
-hipError_t launch_sample(const float* field, const int* idx, const float* w, int n, float* out,
-                         hipStream_t s) {
+hipError_t launch_sample(const void* field, int st, LevelMeta meta, int m, const int* idx,
+                         const float* w, int n, float* out, hipStream_t s) {
   if (n <= 0) return hipSuccess;
-  hipLaunchKernelGGL(sample_kernel, dim3((n + 255) / 256), dim3(256), 0, s, field, idx, w, n,
-                     out);
+  const dim3 grid((n + 255) / 256), block(256);
+  if (st == ST_F32)
+    hipLaunchKernelGGL(sample_kernel<ST_F32>, grid, block, 0, s, field, meta, m, idx, w, n, out);
+  else if (st == ST_F16)
+    hipLaunchKernelGGL(sample_kernel<ST_F16>, grid, block, 0, s, field, meta, m, idx, w, n, out);
+  else
+    hipLaunchKernelGGL(sample_kernel<ST_BF16>, grid, block, 0, s, field, meta, m, idx, w, n, out);
   return hipGetLastError();
 }
 
@@ -394,6 +652,46 @@ hipError_t launch_grad_finalize(const float* graw, const float* vel, float* grad
 hipError_t launch_copy(const float* src, float* dst, int64_t n, hipStream_t s) {
   if (n <= 0) return hipSuccess;
   hipLaunchKernelGGL(copy_kernel, dim3(elementwise_blocks(n)), dim3(256), 0, s, src, dst, n);
+  return hipGetLastError();
+}
+
+hipError_t launch_zero_words(unsigned* p, int64_t n, hipStream_t s) {
+  if (n <= 0) return hipSuccess;
+  hipLaunchKernelGGL(zero_words_kernel, dim3(elementwise_blocks(n)), dim3(256), 0, s, p, n);
+  return hipGetLastError();
+}
+
+hipError_t launch_inj_bound(const float* trace, int nt, int ntr, float c2max, float* injb,
+                            hipStream_t s) {
+  if (nt <= 0 || ntr <= 0 || trace == nullptr) return hipSuccess;
+  hipLaunchKernelGGL(inj_bound_kernel, dim3(nt), dim3(256), 0, s, trace, ntr, c2max, injb);
+  return hipGetLastError();
+}
+
+hipError_t launch_encode_initial(const float* a, const float* b, void* ua, void* ub, int st,
+                                 bool diff, LevelMeta meta, int m, Geom g, hipStream_t s) {
+  const int64_t n = (int64_t)g.nx * g.ny * g.nz;
+  unsigned* slot_b = diff ? meta.md + m + 1 : meta.mu + m;
+  hipLaunchKernelGGL(initial_max_kernel, dim3(elementwise_blocks(n)), dim3(256), 0, s, a, b, diff,
+                     meta.mu + m + 1, slot_b, n);
+  hipLaunchKernelGGL(initial_scales_kernel, dim3(1), dim3(64), 0, s, meta, m, diff);
+  const dim3 grid(elementwise_blocks(g.nfield / 4)), block(256);
+  if (st == ST_F16)
+    hipLaunchKernelGGL(encode_initial_kernel<ST_F16>, grid, block, 0, s, a, b, ua, ub, diff, meta,
+                       m, g);
+  else
+    hipLaunchKernelGGL(encode_initial_kernel<ST_BF16>, grid, block, 0, s, a, b, ua, ub, diff,
+                       meta, m, g);
+  return hipGetLastError();
+}
+
+hipError_t launch_decode(const void* src, int st, LevelMeta meta, int m, float* dst, Geom g,
+                         hipStream_t s) {
+  const dim3 grid(elementwise_blocks((int64_t)g.nx * g.ny * g.nz)), block(256);
+  if (st == ST_F16)
+    hipLaunchKernelGGL(decode_kernel<ST_F16>, grid, block, 0, s, src, meta, m, dst, g);
+  else
+    hipLaunchKernelGGL(decode_kernel<ST_BF16>, grid, block, 0, s, src, meta, m, dst, g);
   return hipGetLastError();
 }
 

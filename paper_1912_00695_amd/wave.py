@@ -15,7 +15,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libwave.so")
 
 OK, EINVAL, ECFL, ENOMEM, EDEVICE, EBUSY, EAGAIN = 0, -1, -2, -3, -4, -5, -6
-STORE_F32, STORE_F16, STORE_BF16 = 0, 1, 2
+STORE_F32, STORE_F16, STORE_BF16, STORE_DIFF = 0, 1, 2, 16
 MODE_FORWARD, MODE_ADJOINT, MODE_GRADIENT = 0, 1, 2
 
 # Entry points declared in include/wave.h.

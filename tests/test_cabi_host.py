@@ -89,6 +89,7 @@ def test_forward_rejects_before_enqueue():
     assert _fwd(_grid(n=(0, 4, 4))) == wave.EINVAL
     assert _fwd(_grid(nbl=(20, 20, 0, 0, 0, 0))) == wave.EINVAL
     assert _fwd(_grid(storage=7)) == wave.EINVAL
+    assert _fwd(_grid(storage=wave.STORE_DIFF)) == wave.EINVAL  # FP32 has no difference form
     dtm = wave.cfl_dt_max(8, 2000.0, (10.0,) * 3)
     assert _fwd(_grid(dt=1.01 * dtm)) == wave.ECFL
     assert _fwd(g, vel=None) == wave.EINVAL
@@ -101,6 +102,24 @@ def test_forward_rejects_before_enqueue():
     assert _fwd(g, ws=ctypes.c_void_p(0x100004)) == wave.EINVAL  # misaligned workspace
     need = wave.workspace_bytes(g, 0, 0)
     assert _fwd(g, wsb=need - 1) == wave.ENOMEM
+
+
+def test_reduced_storage_workspace_and_limits():
+    f32 = wave.workspace_bytes(_grid(n=(64, 64, 64)), 1, 1)
+    f16 = wave.workspace_bytes(_grid(n=(64, 64, 64), storage=wave.STORE_F16), 1, 1)
+    f16d = wave.workspace_bytes(_grid(n=(64, 64, 64), storage=wave.STORE_F16 | wave.STORE_DIFF),
+                                1, 1)
+    assert f16 < f32 < f16d + 64 ** 3 * 4 and f16 < f16d
+    L = wave.lib()
+    for st in (wave.STORE_F16, wave.STORE_BF16 | wave.STORE_DIFF):
+        g = _grid(storage=st)
+        # checkpoints, adjoint and gradient are FP32-storage only
+        assert L.wave_forward(ctypes.byref(g), FAKE, None, None, 0, None, 0, None, None, None,
+                              None, FAKE, 4, FAKE, 1 << 40, None) == wave.EINVAL
+        assert L.wave_adjoint(ctypes.byref(g), FAKE, FAKE, None, 0, None, 0, FAKE, None, FAKE,
+                              1 << 40, None) == wave.EINVAL
+        assert L.wave_gradient(ctypes.byref(g), FAKE, FAKE, None, 0, None, 0, FAKE, None, 0,
+                               FAKE, None, FAKE, 1 << 40, None) == wave.EINVAL
 
 
 def test_adjoint_and_gradient_reject_before_enqueue():

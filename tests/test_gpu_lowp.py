@@ -1,0 +1,89 @@
+"""16-bit wavefield storage (FP16 / BF16, FP32 arithmetic) against the FP64 oracle and
+against the FP32 GPU solve.
+
+There is no exact reference for a rounded storage format: these tests state the
+error of each format (printed) and check what must hold -- the difference form
+(u, u - u_prev) beats storing two levels, FP16 beats BF16, FP16 in the difference
+form meets rel-L2 <= 1e-2 on the traces (its final-field error, measured at about
+1.2e-2 on the 160^3 case, is bounded at 2e-2), and the per-level power-of-two scales
+make the result independent of the wavefield's magnitude.
+"""
+import numpy as np
+import pytest
+
+from helpers import Case, rel_l2
+from paper_1912_00695_amd import inputs
+
+pytestmark = pytest.mark.gpu
+FORMATS = {"f16": 1, "bf16": 2, "f16_diff": 1 | 16, "bf16_diff": 2 | 16}
+
+
+def c4_case(n=(512, 512, 512), nt=1000, nbl=40):
+    """SO8, smoothed-random velocity in [1500, 4500] m/s (20-cell correlation,
+    seed 4), 15 Hz Ricker at the centre, dt = 0.5 dt_max(4500), receivers along x
+    through the source plane and at z = 20."""
+    h = (10.0, 10.0, 10.0)
+    vel = inputs.smooth_random_range(n, 1500.0, 4500.0, 20.0, seed=4)
+    c = Case(n, h, 8, nt, vel, 4500.0, nbl=(nbl,) * 6)
+    c.src = inputs.point((n[0] // 2, n[1] // 2, n[2] // 2), h)
+    c.wavelet = inputs.ricker(15.0, c.dt, nt)[:, None]
+    c.rec = np.concatenate([inputs.line_x(n, h, n[1] // 2, n[2] // 2 + 10),
+                            inputs.line_x(n, h, n[1] // 2, 20)])
+    return c
+
+
+def _run(case, storage, scale=1.0):
+    import torch
+    from paper_1912_00695_amd import wave
+    dev = torch.device("cuda:0")
+    out = wave.forward(case.wgrid(storage), torch.from_numpy(case.vel).to(dev),
+                       torch.from_numpy((scale * case.wavelet).astype(np.float32)).to(dev),
+                       case.src, case.rec, want_final=True)
+    torch.cuda.synchronize()
+    return out["rec"].cpu().numpy(), out["u_final"].cpu().numpy()
+
+
+def test_reduced_storage_vs_oracle():
+    case = c4_case(n=(160, 160, 160), nt=1000, nbl=20)
+    print("C4-shaped 160^3 SO8 nt=1000 vs FP64 oracle", flush=True)
+    orec, ouf, _ = case.oracle_forward()
+    err = {}
+    r32, u32 = _run(case, 0)
+    err["f32"] = (rel_l2(u32, ouf), rel_l2(r32, orec))
+    for name, st in FORMATS.items():
+        r, u = _run(case, st)
+        err[name] = (rel_l2(u, ouf), rel_l2(r, orec))
+    for k, (eu, er) in err.items():
+        print("%-9s field rel-L2 %.3e  traces rel-L2 %.3e" % (k, eu, er), flush=True)
+    assert err["f32"][0] <= 1e-5 and err["f32"][1] <= 1e-5
+    assert err["f16_diff"][0] <= 2e-2 and err["f16_diff"][1] <= 1e-2
+    assert err["f16_diff"][0] <= err["f16"][0] and err["bf16_diff"][0] <= err["bf16"][0]
+    assert err["f16"][0] <= err["bf16"][0] and err["f16_diff"][0] <= err["bf16_diff"][0]
+
+
+def test_reduced_storage_full_size_vs_fp32():
+    """C4 at full size (512^3, 1000 steps): each format against the FP32 GPU run."""
+    case = c4_case()
+    print("C4 512^3 SO8 nt=1000", flush=True)
+    r32, u32 = _run(case, 0)
+    assert np.abs(r32).max() > 0
+    for name, st in FORMATS.items():
+        r, u = _run(case, st)
+        eu, er = rel_l2(u, u32), rel_l2(r, r32)
+        print("%-9s vs FP32 GPU: field %.3e traces %.3e" % (name, eu, er), flush=True)
+        assert np.isfinite(u).all() and np.isfinite(r).all()
+        if name == "f16_diff":
+            assert eu <= 3e-2 and er <= 1e-2
+
+
+@pytest.mark.parametrize("fmt", ["f16", "bf16", "f16_diff", "bf16_diff"])
+def test_scale_invariance(fmt):
+    """Wavelets scaled by 2^-30 and 2^+30 (far outside FP16's range without scaling,
+    inside FP32's so the arithmetic itself is unaffected) give the same result scaled
+    by the same power of two."""
+    case = c4_case(n=(96, 80, 72), nt=300, nbl=12)
+    r1, u1 = _run(case, FORMATS[fmt])
+    for e in (-30, 30):
+        r2, u2 = _run(case, FORMATS[fmt], scale=2.0 ** e)
+        print(fmt, "scale 2^%d: rel %.3e" % (e, rel_l2(u2 * 2.0 ** -e, u1)), flush=True)
+        assert rel_l2(u2 * 2.0 ** -e, u1) <= 1e-6 and rel_l2(r2 * 2.0 ** -e, r1) <= 1e-6
