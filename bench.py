@@ -152,6 +152,54 @@ def reduced_precision_leg(dev):
     return res
 
 
+def serving_leg(dev, nreq):
+    """The serving workload: Poisson arrivals at 20/s (seed 5) of forward shots drawn
+    from {96^3, 128^3, 192^3, 256^3, 160x160x320} x SO {4, 8} x nt in [200, 1000],
+    layered 1500-4500 m/s models, 20-cell sponge, receiver line at z = 20; then the
+    first 40 of the same requests submitted at once (saturated engine) and solved one
+    by one with wave_forward, for the batched-vs-plain throughput."""
+    import numpy as np
+    import torch
+    from paper_1912_00695_amd import serving, wave
+    res = {}
+    with serving.Engine(96 << 30, 64) as eng:
+        st, recs = serving.run_poisson(eng, nreq, 20.0, seed=5, log=log)
+    ok = sum(1 for r in recs if r["status"] == 0)
+    upd = sum(r["updates"] for r in recs)
+    res["poisson"] = {"requests": nreq, "rate_per_s": 20.0, "completed": ok,
+                      "p50_latency_s": round(st["p50_latency_s"], 4),
+                      "p99_latency_s": round(st["p99_latency_s"], 4),
+                      "mean_latency_s": round(st["mean_latency_s"], 4),
+                      "aggregate_gpts": round(upd / st["span_s"] / 1e9, 2),
+                      "offered_gpts": round(upd / (nreq / 20.0) / 1e9, 2),
+                      "busy_gpts": round(st["total_gpt"] / max(st["busy_s"], 1e-9), 2),
+                      "max_resident": st["max_resident"], "graph_builds": st["graph_builds"]}
+    log("serving poisson: %s" % res["poisson"])
+    rng = np.random.default_rng(6)
+    reqs = [serving.mixed_request(rng) for _ in range(40)]
+    upd = sum(r["updates"] for r in reqs)
+    with serving.Engine(96 << 30, 64) as eng:
+        t0 = time.perf_counter()
+        for r in reqs:
+            eng.submit(r["grid"], r["vel"], r["wavelet"], r["src"], r["rec"])
+        eng.drain(900)
+        t_batched = time.perf_counter() - t0
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for r in reqs:
+        wave.forward(r["grid"], torch.from_numpy(r["vel"]).to(dev),
+                     torch.from_numpy(r["wavelet"]).to(dev), r["src"], r["rec"])["rec"].cpu()
+    torch.cuda.synchronize()
+    t_plain = time.perf_counter() - t0
+    res["saturated_40"] = {"batched_gpts": round(upd / t_batched / 1e9, 2),
+                           "plain_sequential_gpts": round(upd / t_plain / 1e9, 2),
+                           "speedup": round(t_plain / t_batched, 3),
+                           "note": "same requests, bitwise-identical results; both include "
+                                   "host->device upload of each request's inputs"}
+    log("serving saturated: %s" % res["saturated_40"])
+    return res
+
+
 def cpu_baseline(P, target_s=20.0):
     """The FP64 oracle on the host cores, on a bounded number of time steps of the
     same 256^3 SO8 workload."""
@@ -181,6 +229,9 @@ def main():
     ap.add_argument("--so", type=int, default=8)
     ap.add_argument("--no-sweep", action="store_true")
     ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--no-serving", action="store_true")
+    ap.add_argument("--serving-requests", type=int, default=300,
+                    help="requests in the Poisson serving stream (rate 20/s)")
     ap.add_argument("--only-timed", action="store_true",
                     help="run only the timed solves (for profiler runs)")
     ap.add_argument("--with-copy", action="store_true",
@@ -262,6 +313,8 @@ def main():
         del S
     if not args.no_sweep:
         out["lowp_512_so8"] = reduced_precision_leg(dev)
+    if not args.no_serving:
+        out["serving"] = serving_leg(dev, args.serving_requests)
     if not args.no_cpu:
         log("cpu baseline (oracle) ...")
         out["cpu_baseline"] = cpu_baseline(P)

@@ -157,6 +157,62 @@ int wave_gradient(const wave_grid* g, const float* vel, const float* wavelet,
                   float* grad_vel, float* grad_wavelet, void* workspace, size_t ws_bytes,
                   void* hip_stream);
 
+/* ---------------------------------------------------------------------------
+ * Serving: continuous batching of independent forward shots on one GPU.
+ *
+ * An engine owns a device memory pool of hbm_budget_bytes, allocated once by
+ * wave_engine_create, and a worker thread. Submitted requests are admitted
+ * first-come first-served (later requests that fit may overtake one that does
+ * not) whenever a slot and pool space are free; resident shots of each space
+ * order advance together, one batched launch per step, replayed as captured
+ * HIP graphs while other requests upload. A shot's result is bitwise identical
+ * to the same request alone on the engine and to wave_forward of the request.
+ * FP32 storage only. Each request is the forward problem of wave_forward (zero
+ * initial state). */
+typedef struct {
+  wave_grid grid;
+  const float* vel_h;        /* [nz][ny][nx] m/s (host; copied at submit)           */
+  const float* wavelet_h;    /* [nt][nsrc] (host; copied at submit)                 */
+  const double* src_xyz_h;   /* [nsrc][3] metres (host; copied at submit)           */
+  int32_t nsrc;
+  const double* rec_xyz_h;   /* [nrec][3] metres (host; copied at submit)           */
+  int32_t nrec;
+  float* rec_out_h;          /* [nt][nrec] host buffer filled by the engine when the
+                                request completes; must stay valid until then      */
+} wave_request;
+
+typedef struct {
+  int32_t status;            /* WAVE_OK done, WAVE_EAGAIN queued/running, else error */
+  double t_submit, t_admit, t_done;  /* engine clock [s] (steady clock)              */
+} wave_result;
+
+typedef struct {
+  uint64_t submitted, admitted, completed, rejected, queued, resident;
+  double p50_latency_s, p99_latency_s, mean_latency_s, max_latency_s;  /* submit->done */
+  double total_gpt;          /* grid-point updates of completed shots / 1e9          */
+  double busy_s;             /* time with at least one shot resident                 */
+  double span_s;             /* first submit to last completion                      */
+  uint64_t graph_builds, replays, max_resident;
+  size_t max_pool_bytes;     /* high-water mark of pool bytes in use                 */
+} wave_stats;
+
+/* Create an engine with a device pool of hbm_budget_bytes (allocated here, on the
+ * current device) and at most max_slots resident shots. */
+int wave_engine_create(size_t hbm_budget_bytes, int max_slots, void** engine);
+/* Queue a request; its inputs are copied. WAVE_EBUSY if it can never fit the
+ * budget; validation errors as for wave_forward. *id identifies it. */
+int wave_engine_submit(void* engine, const wave_request* req, uint64_t* id);
+/* Non-blocking: the request's status (WAVE_EAGAIN until done), times in *res. */
+int wave_engine_poll(void* engine, uint64_t id, wave_result* res);
+/* Counters and latency percentiles (nearest rank) over completed requests. */
+int wave_engine_stats(void* engine, wave_stats* st);
+/* Block until nothing is queued or resident, or timeout_s passes (WAVE_EAGAIN). */
+int wave_engine_drain(void* engine, double timeout_s);
+/* Pool bytes one request of this shape occupies while resident (0 if invalid). */
+size_t wave_engine_request_bytes(const wave_grid* g, int nsrc, int nrec);
+/* Stop the worker, wait for the device, free the pool. */
+void wave_engine_destroy(void* engine);
+
 /* Human-readable name of a status code (static string). */
 const char* wave_status_string(int status);
 

@@ -11,13 +11,10 @@
 #include <vector>
 
 #include "../../include/wave.h"
+#include "wave_host.h"
 #include "wave_internal.h"
 
 namespace wave {
-namespace {
-
-constexpr size_t kAlign = 256;
-constexpr int kDefaultCkpt = 50;
 
 size_t align_up(size_t v) { return (v + kAlign - 1) / kAlign * kAlign; }
 
@@ -73,10 +70,6 @@ int env_int(const char* name, int dflt) {
   return std::atoi(s);
 }
 
-struct Tiling {
-  int ntile_x, ntile_y, nchunk, zchunk, nblocks;
-};
-
 // z-chunking: aim at ~512 workgroups (two per CU) with chunks of 8..32 planes.
 // Longer chunks amortise the 2r planes each chunk re-reads to prime its z queue;
 // measured on MI355X at 256^3 SO8, 32-plane chunks beat 16 (1024 workgroups) by
@@ -106,21 +99,8 @@ int64_t max_tiles(const Geom& G) {
 
 // ---------------------------------------------------------------------------
 // Workspace layout.
-struct PointTables {   // offsets into the workspace
-  size_t tile_beg, ent, csr_idx, csr_w, samp_idx, samp_w;
-};
-
 int store_kind(const wave_grid* g) { return g->storage & ~WAVE_STORE_DIFF; }
 bool store_diff(const wave_grid* g) { return (g->storage & WAVE_STORE_DIFF) != 0; }
-
-struct Layout {
-  size_t c2, bx, by, bz, u[2], d, meta;
-  PointTables pts[2];  // 0: sources, 1: receivers
-  size_t tables_beg, tables_end;
-  size_t graw, lam[2], seg, ick;  // gradient mode
-  int ckpt_every, nseg;
-  size_t total;
-};
 
 Layout make_layout(const wave_grid* g, int nsrc, int nrec, int mode, int ckpt_every) {
   const Geom G = make_geom(g);
@@ -205,13 +185,6 @@ bool points_ok(const wave_grid* g, const double* xyz, int np) {
   return true;
 }
 
-// Host image of the table region, uploaded with one copy.
-struct Blob {
-  std::vector<char> bytes;
-  size_t base;
-  template <class T>
-  T* at(size_t off) { return reinterpret_cast<T*>(bytes.data() + (off - base)); }
-};
 
 void build_point_tables(const wave_grid* g, const Geom& G, const Tiling& T, const double* xyz,
                         int np, const PointTables& P, Blob& B) {
@@ -294,27 +267,8 @@ void sponge_1d(int n, int lo, int hi, double h, double vmax, double dt, float* b
 
 void delete_blob(void* p) { delete static_cast<Blob*>(p); }
 
-// Common per-call state.
-struct Ctx {
-  const wave_grid* g;
-  Geom G;
-  Tiling T;
-  Layout L;
-  char* ws;
-  hipStream_t s;
-  double wx[MAXR + 1], wy[MAXR + 1], wz[MAXR + 1], wc;
-  template <class T>
-  T* at(size_t off) const { return reinterpret_cast<T*>(ws + off); }
-};
-
-#define HIP_TRY(x)                          \
-  do {                                      \
-    if ((x) != hipSuccess) return WAVE_EDEVICE; \
-  } while (0)
-
-int setup(Ctx& C, const wave_grid* g, const float* vel, const double* src, int nsrc,
-          const double* rec, int nrec, int mode, int ckpt_every, void* ws, size_t ws_bytes,
-          void* stream) {
+int init_ctx(Ctx& C, const wave_grid* g, int nsrc, int nrec, int mode, int ckpt_every, void* ws,
+             size_t ws_bytes, void* stream) {
   C.g = g;
   C.G = make_geom(g);
   C.T = make_tiling(C.G);
@@ -337,7 +291,12 @@ int setup(Ctx& C, const wave_grid* g, const float* vel, const double* src, int n
   for (int q = 2; q <= g->so / 2; ++q)
     wc -= 2.0 * ((double)(float)C.wx[q] + (double)(float)C.wy[q] + (double)(float)C.wz[q]);
   C.wc = wc;
-  // host tables
+  return WAVE_OK;
+}
+
+// Host image of the tables (sponge profiles, injection and sampling tables).
+Blob* build_blob(const Ctx& C, const double* src, int nsrc, const double* rec, int nrec) {
+  const wave_grid* g = C.g;
   Blob* B = new Blob;
   B->base = C.L.tables_beg;
   B->bytes.assign(C.L.tables_end - C.L.tables_beg, 0);
@@ -346,6 +305,15 @@ int setup(Ctx& C, const wave_grid* g, const float* vel, const double* src, int n
   sponge_1d(g->nz, g->nbl[4], g->nbl[5], g->hz, g->vmax, g->dt, B->at<float>(C.L.bz));
   build_point_tables(g, C.G, C.T, src, nsrc, C.L.pts[0], *B);
   build_point_tables(g, C.G, C.T, rec, nrec, C.L.pts[1], *B);
+  return B;
+}
+
+int setup(Ctx& C, const wave_grid* g, const float* vel, const double* src, int nsrc,
+          const double* rec, int nrec, int mode, int ckpt_every, void* ws, size_t ws_bytes,
+          void* stream) {
+  int st = init_ctx(C, g, nsrc, nrec, mode, ckpt_every, ws, ws_bytes, stream);
+  if (st) return st;
+  Blob* B = build_blob(C, src, nsrc, rec, nrec);
   if (hipMemcpyAsync(C.ws + C.L.tables_beg, B->bytes.data(), B->bytes.size(),
                      hipMemcpyHostToDevice, C.s) != hipSuccess) {
     delete B;
@@ -471,7 +439,6 @@ int validate(const wave_grid* g) {
   return WAVE_OK;
 }
 
-}  // namespace
 }  // namespace wave
 
 using namespace wave;

@@ -1,0 +1,584 @@
+// wave_engine.cpp -- continuous-batching shot server behind include/wave.h.
+//
+// One engine owns one HBM pool (allocated once, at create), a descriptor array of
+// resident shots, and a worker thread that drives the GPU:
+//   * submit() copies a request's inputs to the host side of the engine and queues
+//     it (a request that can never fit the budget is rejected with WAVE_EBUSY);
+//   * the worker admits queued requests first-come first-served, skipping ahead to
+//     later ones that fit when the head does not, whenever a slot and pool space
+//     are free; admission uploads the inputs and builds the shot's tables on an
+//     upload stream while resident shots keep running;
+//   * resident shots of each space order advance together: a captured graph of
+//     kReplaySteps launches of the batched step kernel per space order is
+//     replayed; per-shot step counters live in device memory, so one graph serves
+//     any mix of shots at any step, and is re-captured only when the set of
+//     resident shots changes;
+//   * after each replay the worker reads the counters back, retires finished
+//     shots (traces copied to the caller's host buffer, pool space freed,
+//     latency recorded) and admits more.
+// Every shot's arithmetic is the single-shot kernel's (shared tile function), so
+// a result does not depend on the batch it ran in.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <chrono>
+#include <condition_variable>
+#include <cstring>
+#include <deque>
+#include <map>
+#include <memory>
+#include <mutex>
+#include <thread>
+#include <unordered_map>
+#include <vector>
+
+#include "../../include/wave.h"
+#include "wave_host.h"
+#include "wave_internal.h"
+
+namespace wave {
+namespace {
+
+constexpr int kReplaySteps = 8;  // launches per space order in one graph replay (even)
+
+double now_s() {
+  using namespace std::chrono;
+  return duration<double>(steady_clock::now().time_since_epoch()).count();
+}
+
+// First-fit allocator over [0, size) with 256-byte granularity (host bookkeeping
+// of the device pool).
+class PoolAlloc {
+ public:
+  explicit PoolAlloc(size_t size) { free_[0] = size; }
+  bool alloc(size_t bytes, size_t* off) {
+    bytes = align_up(bytes);
+    for (auto it = free_.begin(); it != free_.end(); ++it) {
+      if (it->second >= bytes) {
+        *off = it->first;
+        const size_t rest = it->second - bytes, base = it->first + bytes;
+        free_.erase(it);
+        if (rest) free_[base] = rest;
+        return true;
+      }
+    }
+    return false;
+  }
+  void release(size_t off, size_t bytes) {
+    bytes = align_up(bytes);
+    auto it = free_.emplace(off, bytes).first;
+    auto nx = std::next(it);
+    if (nx != free_.end() && it->first + it->second == nx->first) {
+      it->second += nx->second;
+      free_.erase(nx);
+    }
+    if (it != free_.begin()) {
+      auto pv = std::prev(it);
+      if (pv->first + pv->second == it->first) {
+        pv->second += it->second;
+        free_.erase(it);
+      }
+    }
+  }
+
+ private:
+  std::map<size_t, size_t> free_;  // offset -> length
+};
+
+enum ShotState { QUEUED = 0, UPLOADING = 1, ACTIVE = 2, DONE = 3, FAILED = 4 };
+
+struct Shot {
+  uint64_t id = 0;
+  wave_grid g{};
+  std::vector<float> vel, wavelet;
+  std::vector<double> src, rec;
+  int nsrc = 0, nrec = 0;
+  float* rec_out_h = nullptr;
+  // device placement
+  size_t off = 0, bytes = 0;
+  int slot = -1;
+  Ctx C{};
+  size_t off_wav = 0, off_tr = 0;
+  int nsamp_blocks = 0;
+  std::unique_ptr<Blob> blob;
+  ShotDesc desc{};
+  hipEvent_t ready = nullptr;
+  int state = QUEUED;
+  int counter = 0;
+  int status = WAVE_EAGAIN;
+  double t_submit = 0, t_admit = 0, t_done = 0;
+};
+
+size_t shot_bytes(const wave_grid* g, int nsrc, int nrec) {
+  const Layout L = make_layout(g, nsrc, nrec, WAVE_MODE_FORWARD, 0);
+  return L.total + align_up((size_t)g->nt * nsrc * sizeof(float)) +
+         align_up((size_t)g->nt * nrec * sizeof(float));
+}
+
+class Engine {
+ public:
+  Engine(size_t budget, int max_slots) : budget_(budget), max_slots_(max_slots), alloc_(budget) {}
+
+  int init() {
+    HIP_TRY(hipGetDevice(&device_));
+    HIP_TRY(hipMalloc(&pool_, budget_));
+    HIP_TRY(hipMalloc(&d_desc_, sizeof(ShotDesc) * max_slots_));
+    table_cap_ = 1 << 20;
+    for (int k = 0; k < 2; ++k) HIP_TRY(hipMalloc(&d_table_[k], sizeof(BatchEntry) * table_cap_));
+    HIP_TRY(hipMalloc(&d_slots_, sizeof(int) * max_slots_));
+    HIP_TRY(hipMalloc(&d_counts_, sizeof(int) * max_slots_));
+    HIP_TRY(hipHostMalloc(&h_counts_, sizeof(int) * max_slots_, hipHostMallocDefault));
+    HIP_TRY(hipStreamCreateWithFlags(&s_exec_, hipStreamNonBlocking));
+    HIP_TRY(hipStreamCreateWithFlags(&s_up_, hipStreamNonBlocking));
+    slot_used_.assign(max_slots_, 0);
+    worker_ = std::thread([this] { loop(); });
+    return WAVE_OK;
+  }
+
+  ~Engine() {
+    {
+      std::lock_guard<std::mutex> lk(mu_);
+      stop_ = true;
+    }
+    cv_.notify_all();
+    if (worker_.joinable()) worker_.join();
+    (void)hipSetDevice(device_);
+    if (s_exec_) (void)hipStreamSynchronize(s_exec_);
+    if (s_up_) (void)hipStreamSynchronize(s_up_);
+    if (gexec_) (void)hipGraphExecDestroy(gexec_);
+    for (auto& kv : shots_)
+      if (kv.second->ready) (void)hipEventDestroy(kv.second->ready);
+    if (s_exec_) (void)hipStreamDestroy(s_exec_);
+    if (s_up_) (void)hipStreamDestroy(s_up_);
+    if (h_counts_) (void)hipHostFree(h_counts_);
+    if (d_counts_) (void)hipFree(d_counts_);
+    if (d_slots_) (void)hipFree(d_slots_);
+    for (int k = 0; k < 2; ++k)
+      if (d_table_[k]) (void)hipFree(d_table_[k]);
+    if (d_desc_) (void)hipFree(d_desc_);
+    if (pool_) (void)hipFree(pool_);
+  }
+
+  int submit(const wave_request* r, uint64_t* id) {
+    if (r == nullptr || id == nullptr) return WAVE_EINVAL;
+    const wave_grid* g = &r->grid;
+    int st = validate(g);
+    if (st) return st;
+    if (g->storage != WAVE_STORE_F32) return WAVE_EINVAL;
+    if (r->vel_h == nullptr || r->nsrc < 0 || r->nrec < 0) return WAVE_EINVAL;
+    if (r->nsrc > 0 && r->wavelet_h == nullptr) return WAVE_EINVAL;
+    if (r->nrec > 0 && r->rec_out_h == nullptr) return WAVE_EINVAL;
+    if (!points_ok(g, r->src_xyz_h, r->nsrc) || !points_ok(g, r->rec_xyz_h, r->nrec))
+      return WAVE_EINVAL;
+    auto sh = std::make_unique<Shot>();
+    sh->g = *g;
+    sh->nsrc = r->nsrc;
+    sh->nrec = r->nrec;
+    sh->bytes = shot_bytes(g, r->nsrc, r->nrec);
+    {
+      std::lock_guard<std::mutex> lk(mu_);
+      ++submitted_;
+      if (sh->bytes > budget_) {
+        ++rejected_;
+        return WAVE_EBUSY;
+      }
+    }
+    const size_t n = (size_t)g->nx * g->ny * g->nz;
+    sh->vel.assign(r->vel_h, r->vel_h + n);
+    if (r->nsrc > 0)
+      sh->wavelet.assign(r->wavelet_h, r->wavelet_h + (size_t)g->nt * r->nsrc);
+    if (r->nsrc > 0) sh->src.assign(r->src_xyz_h, r->src_xyz_h + 3 * (size_t)r->nsrc);
+    if (r->nrec > 0) sh->rec.assign(r->rec_xyz_h, r->rec_xyz_h + 3 * (size_t)r->nrec);
+    sh->rec_out_h = r->rec_out_h;
+    sh->t_submit = now_s();
+    {
+      std::lock_guard<std::mutex> lk(mu_);
+      sh->id = ++next_id_;
+      *id = sh->id;
+      if (first_submit_ == 0) first_submit_ = sh->t_submit;
+      queue_.push_back(sh.get());
+      shots_[sh->id] = std::move(sh);
+    }
+    cv_.notify_all();
+    return WAVE_OK;
+  }
+
+  int poll(uint64_t id, wave_result* res) {
+    std::lock_guard<std::mutex> lk(mu_);
+    auto it = shots_.find(id);
+    if (it == shots_.end()) return WAVE_EINVAL;
+    const Shot* s = it->second.get();
+    if (res != nullptr) {
+      res->status = s->status;
+      res->t_submit = s->t_submit;
+      res->t_admit = s->t_admit;
+      res->t_done = s->t_done;
+    }
+    return s->status;
+  }
+
+  int stats(wave_stats* st) {
+    if (st == nullptr) return WAVE_EINVAL;
+    std::lock_guard<std::mutex> lk(mu_);
+    std::memset(st, 0, sizeof(*st));
+    st->submitted = submitted_;
+    st->admitted = admitted_;
+    st->completed = lat_.size();
+    st->rejected = rejected_;
+    st->queued = queue_.size();
+    st->resident = resident_;
+    if (!lat_.empty()) {
+      std::vector<double> v = lat_;
+      std::sort(v.begin(), v.end());
+      auto rank = [&](double q) {  // nearest-rank percentile
+        size_t k = (size_t)std::ceil(q * v.size());
+        return v[std::min(v.size(), std::max<size_t>(k, 1)) - 1];
+      };
+      st->p50_latency_s = rank(0.50);
+      st->p99_latency_s = rank(0.99);
+      double sum = 0;
+      for (double x : v) sum += x;
+      st->mean_latency_s = sum / v.size();
+      st->max_latency_s = v.back();
+    }
+    st->total_gpt = total_updates_ / 1e9;
+    st->busy_s = busy_s_;
+    st->span_s = last_done_ > first_submit_ ? last_done_ - first_submit_ : 0.0;
+    st->graph_builds = graph_builds_;
+    st->replays = replays_;
+    st->max_resident = max_resident_;
+    st->max_pool_bytes = max_pool_bytes_;
+    return WAVE_OK;
+  }
+
+  int drain(double timeout_s) {
+    const double t_end = now_s() + timeout_s;
+    std::unique_lock<std::mutex> lk(mu_);
+    while (!(queue_.empty() && resident_ == 0)) {
+      if (now_s() > t_end) return WAVE_EAGAIN;
+      done_cv_.wait_for(lk, std::chrono::milliseconds(5));
+    }
+    return WAVE_OK;
+  }
+
+ private:
+  // ---- worker ----
+  void loop() {
+    (void)hipSetDevice(device_);
+    std::vector<Shot*> resident;  // UPLOADING or ACTIVE, worker-owned view
+    bool dirty = true;
+    double busy_t0 = 0;
+    while (true) {
+      std::vector<Shot*> incoming;
+      {
+        std::unique_lock<std::mutex> lk(mu_);
+        if (stop_) break;
+        if (resident.empty() && queue_.empty()) {
+          cv_.wait_for(lk, std::chrono::milliseconds(2));
+          continue;
+        }
+        // admission: FIFO with skip-ahead over requests that fit
+        for (auto it = queue_.begin(); it != queue_.end();) {
+          Shot* s = *it;
+          int slot = free_slot();
+          size_t off = 0;
+          if (slot < 0) break;
+          if (!alloc_.alloc(s->bytes, &off)) {
+            ++it;
+            continue;
+          }
+          s->off = off;
+          s->slot = slot;
+          slot_used_[slot] = 1;
+          pool_used_ += align_up(s->bytes);
+          max_pool_bytes_ = std::max(max_pool_bytes_, pool_used_);
+          ++admitted_;
+          ++resident_;
+          max_resident_ = std::max<uint64_t>(max_resident_, resident_);
+          s->t_admit = now_s();
+          incoming.push_back(s);
+          it = queue_.erase(it);
+        }
+      }
+      for (Shot* s : incoming) {
+        if (start_upload(s) != WAVE_OK) {
+          fail(s);
+          continue;
+        }
+        resident.push_back(s);
+      }
+      // promote finished uploads
+      for (Shot* s : resident)
+        if (s->state == UPLOADING && hipEventQuery(s->ready) == hipSuccess) {
+          s->state = ACTIVE;
+          s->blob.reset();
+          std::vector<float>().swap(s->vel);
+          dirty = true;
+        }
+      std::vector<Shot*> active;
+      for (Shot* s : resident)
+        if (s->state == ACTIVE) active.push_back(s);
+      if (active.empty()) {
+        if (!resident.empty()) std::this_thread::sleep_for(std::chrono::microseconds(50));
+        continue;
+      }
+      if (busy_t0 == 0) busy_t0 = now_s();
+      if (dirty) {
+        if (rebuild_graph(active) != WAVE_OK) {
+          for (Shot* s : active) fail(s);
+          resident.clear();
+          continue;
+        }
+        dirty = false;
+      }
+      // one replay, then read back the counters
+      if (hipGraphLaunch(gexec_, s_exec_) != hipSuccess ||
+          launch_gather_counters(d_desc_, d_slots_, (int)active.size(), d_counts_, s_exec_) !=
+              hipSuccess ||
+          hipMemcpyAsync(h_counts_, d_counts_, sizeof(int) * active.size(),
+                         hipMemcpyDeviceToHost, s_exec_) != hipSuccess ||
+          hipStreamSynchronize(s_exec_) != hipSuccess) {
+        for (Shot* s : resident) fail(s);
+        resident.clear();
+        continue;
+      }
+      ++replays_;
+      // retire
+      std::vector<Shot*> keep;
+      for (size_t i = 0; i < active.size(); ++i) active[i]->counter = h_counts_[i];
+      for (Shot* s : resident) {
+        if (s->state == ACTIVE && s->counter > s->g.nt) {
+          retire(s);
+          dirty = true;
+        } else {
+          keep.push_back(s);
+        }
+      }
+      resident.swap(keep);
+      if (resident.empty() && busy_t0 > 0) {
+        std::lock_guard<std::mutex> lk(mu_);
+        busy_s_ += now_s() - busy_t0;
+        busy_t0 = 0;
+      }
+    }
+  }
+
+  int free_slot() const {
+    for (int i = 0; i < max_slots_; ++i)
+      if (!slot_used_[i]) return i;
+    return -1;
+  }
+
+  // Device layout of a shot inside its pool region: the forward-mode workspace,
+  // then the wavelet, then the traces.
+  int start_upload(Shot* s) {
+    char* base = static_cast<char*>(pool_) + s->off;
+    const wave_grid* g = &s->g;
+    int st = init_ctx(s->C, g, s->nsrc, s->nrec, WAVE_MODE_FORWARD, 0, base, s->bytes, s_up_);
+    if (st) return st;
+    s->C.g = &s->g;
+    s->off_wav = s->C.L.total;
+    s->off_tr = s->off_wav + align_up((size_t)g->nt * s->nsrc * sizeof(float));
+    s->blob.reset(build_blob(s->C, s->src.data(), s->nsrc, s->rec.data(), s->nrec));
+    float* U0 = s->C.at<float>(s->C.L.u[0]);
+    float* U1 = s->C.at<float>(s->C.L.u[1]);
+    // the velocity is staged in u[1] (dense fits in pitched), turned into c2, then
+    // both u levels are cleared
+    HIP_TRY(hipMemcpyAsync(base + s->C.L.tables_beg, s->blob->bytes.data(), s->blob->bytes.size(),
+                           hipMemcpyHostToDevice, s_up_));
+    HIP_TRY(hipMemcpyAsync(U1, s->vel.data(), s->vel.size() * sizeof(float),
+                           hipMemcpyHostToDevice, s_up_));
+    HIP_TRY(launch_prep_c2(U1, s->C.at<float>(s->C.L.c2), s->C.G, g->dt, s_up_));
+    HIP_TRY(launch_pack(nullptr, U0, s->C.G, s_up_));
+    HIP_TRY(launch_pack(nullptr, U1, s->C.G, s_up_));
+    float* wav = reinterpret_cast<float*>(base + s->off_wav);
+    if (s->nsrc > 0)
+      HIP_TRY(hipMemcpyAsync(wav, s->wavelet.data(), s->wavelet.size() * sizeof(float),
+                             hipMemcpyHostToDevice, s_up_));
+    ShotDesc& d = s->desc;
+    d.a = base_args(s->C);
+    set_inj(d.a, s->C, 0, s->nsrc, s->nsrc > 0 ? wav : nullptr);
+    set_samp(d.a, s->C, 1, s->nrec, reinterpret_cast<float*>(base + s->off_tr));
+    d.buf[0] = U0;
+    d.buf[1] = U1;
+    d.wavelet = wav;
+    d.traces = reinterpret_cast<float*>(base + s->off_tr);
+    d.nsrc = s->nsrc;
+    d.nrec = s->nrec;
+    d.nt = g->nt;
+    d.cnt[0] = 0;
+    d.cnt[1] = 0;
+    s->nsamp_blocks = s->nrec > 0 ? (s->nrec + NTHREADS - 1) / NTHREADS : 0;
+    HIP_TRY(hipMemcpyAsync(d_desc_ + s->slot, &s->desc, sizeof(ShotDesc), hipMemcpyHostToDevice,
+                           s_up_));
+    HIP_TRY(hipEventCreateWithFlags(&s->ready, hipEventDisableTiming));
+    HIP_TRY(hipEventRecord(s->ready, s_up_));
+    s->state = UPLOADING;
+    return WAVE_OK;
+  }
+
+  // Tables of (shot, tile) per space order, and the captured replay graph.
+  int rebuild_graph(const std::vector<Shot*>& active) {
+    std::map<int, std::vector<BatchEntry>> groups;  // radius -> entries
+    std::vector<int> slots;
+    for (Shot* s : active) {
+      slots.push_back(s->slot);
+      auto& v = groups[s->g.so / 2];
+      for (int t = 0; t < s->C.T.nblocks; ++t) v.push_back(BatchEntry{s->slot, t});
+      for (int k = 0; k < s->nsamp_blocks; ++k) v.push_back(BatchEntry{s->slot, -1 - k});
+    }
+    std::vector<BatchEntry> all;
+    std::vector<std::pair<int, std::pair<int, int>>> segs;  // radius, (offset, count)
+    for (auto& kv : groups) {
+      segs.push_back({kv.first, {(int)all.size(), (int)kv.second.size()}});
+      all.insert(all.end(), kv.second.begin(), kv.second.end());
+    }
+    if ((int)all.size() > table_cap_) return WAVE_ENOMEM;
+    cur_table_ ^= 1;
+    BatchEntry* tab = d_table_[cur_table_];
+    HIP_TRY(hipMemcpyAsync(tab, all.data(), all.size() * sizeof(BatchEntry),
+                           hipMemcpyHostToDevice, s_exec_));
+    HIP_TRY(hipMemcpyAsync(d_slots_, slots.data(), slots.size() * sizeof(int),
+                           hipMemcpyHostToDevice, s_exec_));
+    HIP_TRY(hipStreamSynchronize(s_exec_));
+    hipGraph_t graph = nullptr;
+    HIP_TRY(hipStreamBeginCapture(s_exec_, hipStreamCaptureModeThreadLocal));
+    hipError_t err = hipSuccess;
+    for (int k = 0; k < kReplaySteps && err == hipSuccess; ++k)
+      for (auto& sg : segs) {
+        err = launch_batched(d_desc_, tab + sg.second.first, sg.second.second, sg.first, k & 1,
+                             s_exec_);
+        if (err != hipSuccess) break;
+      }
+    hipError_t e2 = hipStreamEndCapture(s_exec_, &graph);
+    if (err != hipSuccess || e2 != hipSuccess) {
+      if (graph) (void)hipGraphDestroy(graph);
+      return WAVE_EDEVICE;
+    }
+    if (gexec_) (void)hipGraphExecDestroy(gexec_);
+    gexec_ = nullptr;
+    err = hipGraphInstantiate(&gexec_, graph, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(graph);
+    if (err != hipSuccess) return WAVE_EDEVICE;
+    ++graph_builds_;
+    return WAVE_OK;
+  }
+
+  void retire(Shot* s) {
+    bool ok = true;
+    if (s->nrec > 0 && s->rec_out_h != nullptr)
+      ok = hipMemcpyAsync(s->rec_out_h, s->desc.traces, sizeof(float) * (size_t)s->g.nt * s->nrec,
+                          hipMemcpyDeviceToHost, s_exec_) == hipSuccess &&
+           hipStreamSynchronize(s_exec_) == hipSuccess;
+    if (s->ready) {
+      (void)hipEventDestroy(s->ready);
+      s->ready = nullptr;
+    }
+    std::lock_guard<std::mutex> lk(mu_);
+    s->t_done = now_s();
+    s->status = ok ? WAVE_OK : WAVE_EDEVICE;
+    s->state = ok ? DONE : FAILED;
+    alloc_.release(s->off, s->bytes);
+    pool_used_ -= align_up(s->bytes);
+    slot_used_[s->slot] = 0;
+    --resident_;
+    if (ok) {
+      lat_.push_back(s->t_done - s->t_submit);
+      total_updates_ += (double)s->g.nx * s->g.ny * s->g.nz * s->g.nt;
+      last_done_ = s->t_done;
+    }
+    std::vector<float>().swap(s->wavelet);
+    done_cv_.notify_all();
+  }
+
+  void fail(Shot* s) {
+    std::lock_guard<std::mutex> lk(mu_);
+    s->status = WAVE_EDEVICE;
+    s->state = FAILED;
+    s->t_done = now_s();
+    if (s->slot >= 0) {
+      alloc_.release(s->off, s->bytes);
+      pool_used_ -= align_up(s->bytes);
+      slot_used_[s->slot] = 0;
+      s->slot = -1;
+      --resident_;
+    }
+    done_cv_.notify_all();
+  }
+
+  size_t budget_;
+  int max_slots_;
+  int device_ = 0;
+  void* pool_ = nullptr;
+  PoolAlloc alloc_;
+  size_t pool_used_ = 0, max_pool_bytes_ = 0;
+  ShotDesc* d_desc_ = nullptr;
+  BatchEntry* d_table_[2] = {nullptr, nullptr};
+  int table_cap_ = 0, cur_table_ = 0;
+  int* d_slots_ = nullptr;
+  int* d_counts_ = nullptr;
+  int* h_counts_ = nullptr;
+  hipStream_t s_exec_ = nullptr, s_up_ = nullptr;
+  hipGraphExec_t gexec_ = nullptr;
+  std::vector<char> slot_used_;
+  std::thread worker_;
+  std::mutex mu_;
+  std::condition_variable cv_, done_cv_;
+  bool stop_ = false;
+  std::deque<Shot*> queue_;
+  std::unordered_map<uint64_t, std::unique_ptr<Shot>> shots_;
+  uint64_t next_id_ = 0, submitted_ = 0, admitted_ = 0, rejected_ = 0, resident_ = 0;
+  uint64_t max_resident_ = 0, graph_builds_ = 0, replays_ = 0;
+  std::vector<double> lat_;
+  double total_updates_ = 0, busy_s_ = 0, first_submit_ = 0, last_done_ = 0;
+};
+
+}  // namespace
+}  // namespace wave
+
+using wave::Engine;
+
+extern "C" {
+
+int wave_engine_create(size_t hbm_budget_bytes, int max_slots, void** engine) {
+  if (engine == nullptr || max_slots < 1 || max_slots > 4096 || hbm_budget_bytes < 4096)
+    return WAVE_EINVAL;
+  *engine = nullptr;
+  Engine* e = new Engine(hbm_budget_bytes, max_slots);
+  const int st = e->init();
+  if (st != WAVE_OK) {
+    delete e;
+    return st;
+  }
+  *engine = e;
+  return WAVE_OK;
+}
+
+int wave_engine_submit(void* engine, const wave_request* req, uint64_t* id) {
+  if (engine == nullptr) return WAVE_EINVAL;
+  return static_cast<Engine*>(engine)->submit(req, id);
+}
+
+int wave_engine_poll(void* engine, uint64_t id, wave_result* res) {
+  if (engine == nullptr) return WAVE_EINVAL;
+  return static_cast<Engine*>(engine)->poll(id, res);
+}
+
+int wave_engine_stats(void* engine, wave_stats* st) {
+  if (engine == nullptr) return WAVE_EINVAL;
+  return static_cast<Engine*>(engine)->stats(st);
+}
+
+int wave_engine_drain(void* engine, double timeout_s) {
+  if (engine == nullptr) return WAVE_EINVAL;
+  return static_cast<Engine*>(engine)->drain(timeout_s);
+}
+
+void wave_engine_destroy(void* engine) { delete static_cast<Engine*>(engine); }
+
+size_t wave_engine_request_bytes(const wave_grid* g, int nsrc, int nrec) {
+  if (!wave::grid_ok(g) || nsrc < 0 || nrec < 0) return 0;
+  return wave::align_up(wave::shot_bytes(g, nsrc, nrec));
+}
+
+}  // extern "C"

@@ -1,0 +1,76 @@
+// wave_host.h -- host-side helpers shared by the solver entry points
+// (wave_api.cpp) and the serving engine (wave_engine.cpp); internal.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <vector>
+
+#include "../../include/wave.h"
+#include "wave_internal.h"
+
+namespace wave {
+
+constexpr size_t kAlign = 256;
+constexpr int kDefaultCkpt = 50;
+
+struct Tiling {
+  int ntile_x, ntile_y, nchunk, zchunk, nblocks;
+};
+
+struct PointTables {  // offsets into the workspace
+  size_t tile_beg, ent, csr_idx, csr_w, samp_idx, samp_w;
+};
+
+// Workspace layout of one call (offsets from the workspace base).
+struct Layout {
+  size_t c2, bx, by, bz, u[2], d, meta;
+  PointTables pts[2];  // 0: sources, 1: receivers
+  size_t tables_beg, tables_end;
+  size_t graw, lam[2], seg, ick;  // gradient mode
+  int ckpt_every, nseg;
+  size_t total;
+};
+
+// Host image of the table region, uploaded with one copy.
+struct Blob {
+  std::vector<char> bytes;
+  size_t base;
+  template <class T>
+  T* at(size_t off) { return reinterpret_cast<T*>(bytes.data() + (off - base)); }
+};
+
+// Per-call state.
+struct Ctx {
+  const wave_grid* g;
+  Geom G;
+  Tiling T;
+  Layout L;
+  char* ws;
+  hipStream_t s;
+  double wx[MAXR + 1], wy[MAXR + 1], wz[MAXR + 1], wc;
+  template <class T>
+  T* at(size_t off) const { return reinterpret_cast<T*>(ws + off); }
+};
+
+#define HIP_TRY(x)                              \
+  do {                                          \
+    if ((x) != hipSuccess) return WAVE_EDEVICE; \
+  } while (0)
+
+size_t align_up(size_t v);
+bool grid_ok(const wave_grid* g);
+int validate(const wave_grid* g);  // grid_ok + stability limit
+bool points_ok(const wave_grid* g, const double* xyz, int np);
+Geom make_geom(const wave_grid* g);
+Tiling make_tiling(const Geom& G);
+Layout make_layout(const wave_grid* g, int nsrc, int nrec, int mode, int ckpt_every);
+// geometry, tiling, layout and weights of a call on workspace ws (no device work)
+int init_ctx(Ctx& C, const wave_grid* g, int nsrc, int nrec, int mode, int ckpt_every, void* ws,
+             size_t ws_bytes, void* stream);
+Blob* build_blob(const Ctx& C, const double* src, int nsrc, const double* rec, int nrec);
+StepArgs base_args(const Ctx& C);
+void set_inj(StepArgs& a, const Ctx& C, int set, int np, const float* row);
+void set_samp(StepArgs& a, const Ctx& C, int set, int np, float* row);
+
+}  // namespace wave

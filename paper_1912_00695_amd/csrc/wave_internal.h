@@ -94,9 +94,29 @@ struct StepArgs {
   LevelMeta meta;
 };
 
+// Serving: a resident shot and one entry of a batched launch's tile table.
+struct ShotDesc {
+  StepArgs a;              // static per-shot arguments (tables, geometry, weights)
+  float* buf[2];           // the two pitched u buffers: level n lives in buf[n & 1]
+  const float* wavelet;    // [nt][nsrc]
+  float* traces;           // [nt][nrec]
+  int nsrc, nrec, nt;
+  int cnt[2];              // step counter, parity-indexed (see batched_step_kernel)
+};
+struct BatchEntry {
+  int shot;   // slot in the descriptor array
+  int tile;   // stencil tile id >= 0, or -1-k for sampling block k
+};
+
 // Launchers (wave_kernels.hip). All return hipGetLastError() after the launch.
 // st: StoreKind; diff: difference-form storage (reduced precision only).
 hipError_t launch_step(const StepArgs& a, int r, bool grad, int st, bool diff, hipStream_t s);
+// one batched step of every shot in table (space-order radius r, launch parity)
+hipError_t launch_batched(ShotDesc* shots, const BatchEntry* table, int nentries, int r,
+                          int parity, hipStream_t s);
+// out[i] = shots[slots[i]].cnt[0]
+hipError_t launch_gather_counters(const ShotDesc* shots, const int* slots, int n, int* out,
+                                  hipStream_t s);
 // out[i] = sum_c w[8i+c] field[idx[8i+c]], the field decoded with level m's scale
 hipError_t launch_sample(const void* field, int st, LevelMeta meta, int m, const int* idx,
                          const float* w, int n, float* out, hipStream_t s);

@@ -130,8 +130,13 @@ __device__ __forceinline__ float sample_point(const void* f, float dec, const in
 }
 }  // namespace
 
+// One tile of one step: the z-sweep of a TX x TY column block over one z-chunk.
+// Shared by the single-shot kernel and the batched serving kernel, so a shot's
+// values do not depend on what else is in the launch.
 template <int R, bool GRAD, int ST, bool DIFF>
-__global__ void __launch_bounds__(NTHREADS) step_kernel(const StepArgs a) {
+__device__ __forceinline__ void step_tile(const StepArgs& a, const int t, const float dec_c,
+                                          const float dec_p, const float enc_u,
+                                          const float enc_d) {
   constexpr int XH = R <= 4 ? 4 : 8;  // x-halo width in floats (multiple of 4)
   constexpr int XH4 = XH / 4;
   constexpr int LROW4 = NTX + 2 * XH4;  // float4 per LDS row
@@ -141,40 +146,6 @@ __global__ void __launch_bounds__(NTHREADS) step_kernel(const StepArgs a) {
   __shared__ float4 lds[2][LROWS * LROW4];
   __shared__ float4 inj[TY * NTX];
 
-  // Per-level scales of reduced-precision storage: decode cur and prev, choose
-  // the encode scales of the level written here from the previous maxima.
-  float dec_c = 1.f, dec_p = 1.f, enc_u = 1.f, enc_d = 1.f;
-  if constexpr (ST != ST_F32) {
-    const int n = a.level;
-    dec_c = ldexpf(1.f, -a.meta.eu[n + 1]);
-    dec_p = ldexpf(1.f, DIFF ? -a.meta.ed[n + 1] : -a.meta.eu[n]);
-    const float mun = __uint_as_float(a.meta.mu[n + 1]);
-    const float injb = a.meta.injb[n];
-    int eu, ed = 0;
-    if constexpr (DIFF) {
-      // |d^{n+1}| <= |d^n| + c2 |L u^n| + inj, c2 |L| <= 4 under the CFL limit
-      const float bd = __uint_as_float(a.meta.md[n + 1]) + 4.f * mun + injb;
-      ed = scale_exp(bd);
-      eu = scale_exp(mun + bd);
-    } else {
-      eu = scale_exp(8.f * fmaxf(mun, __uint_as_float(a.meta.mu[n])) + injb);
-    }
-    enc_u = ldexpf(1.f, eu);
-    enc_d = ldexpf(1.f, ed);
-    if (blockIdx.x == 0 && threadIdx.x == 0) {
-      a.meta.eu[n + 2] = eu;
-      if (DIFF) a.meta.ed[n + 2] = ed;
-    }
-  }
-
-  const int bid = blockIdx.x;
-  if (bid >= a.nstencil_blocks) {
-    const int r = (bid - a.nstencil_blocks) * NTHREADS + threadIdx.x;
-    if (a.samp_out != nullptr && r < a.nsamp)
-      a.samp_out[r] = sample_point<ST>(a.cur, dec_c, a.samp_idx, a.samp_w, r);
-    return;
-  }
-  const int t = a.xcd_remap ? remap_tile(bid, a.nstencil_blocks) : bid;
   const int tx_t = t % a.ntile_x;
   const int rest = t / a.ntile_x;
   const int ty_t = rest % a.ntile_y;
@@ -409,6 +380,87 @@ __global__ void __launch_bounds__(NTHREADS) step_kernel(const StepArgs a) {
   }
 }
 
+template <int R, bool GRAD, int ST, bool DIFF>
+__global__ void __launch_bounds__(NTHREADS) step_kernel(const StepArgs a) {
+  // Per-level scales of reduced-precision storage: decode cur and prev, choose
+  // the encode scales of the level written here from the previous maxima.
+  float dec_c = 1.f, dec_p = 1.f, enc_u = 1.f, enc_d = 1.f;
+  if constexpr (ST != ST_F32) {
+    const int n = a.level;
+    dec_c = ldexpf(1.f, -a.meta.eu[n + 1]);
+    dec_p = ldexpf(1.f, DIFF ? -a.meta.ed[n + 1] : -a.meta.eu[n]);
+    const float mun = __uint_as_float(a.meta.mu[n + 1]);
+    const float injb = a.meta.injb[n];
+    int eu, ed = 0;
+    if constexpr (DIFF) {
+      // |d^{n+1}| <= |d^n| + c2 |L u^n| + inj, c2 |L| <= 4 under the CFL limit
+      const float bd = __uint_as_float(a.meta.md[n + 1]) + 4.f * mun + injb;
+      ed = scale_exp(bd);
+      eu = scale_exp(mun + bd);
+    } else {
+      eu = scale_exp(8.f * fmaxf(mun, __uint_as_float(a.meta.mu[n])) + injb);
+    }
+    enc_u = ldexpf(1.f, eu);
+    enc_d = ldexpf(1.f, ed);
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
+      a.meta.eu[n + 2] = eu;
+      if (DIFF) a.meta.ed[n + 2] = ed;
+    }
+  }
+  const int bid = blockIdx.x;
+  if (bid >= a.nstencil_blocks) {
+    const int r = (bid - a.nstencil_blocks) * NTHREADS + threadIdx.x;
+    if (a.samp_out != nullptr && r < a.nsamp)
+      a.samp_out[r] = sample_point<ST>(a.cur, dec_c, a.samp_idx, a.samp_w, r);
+    return;
+  }
+  const int t = a.xcd_remap ? remap_tile(bid, a.nstencil_blocks) : bid;
+  step_tile<R, GRAD, ST, DIFF>(a, t, dec_c, dec_p, enc_u, enc_d);
+}
+
+// Serving: one launch advances every active shot of one space order by a step.
+// Block b (after the XCD remap) takes table entry b = (shot, tile); tile < 0 is
+// sampling block -1-tile of that shot. The shot's step n is read from its
+// parity-indexed counter (launches alternate parity), so the same captured
+// launch sequence replays for any mix of shots at any steps. A shot whose n
+// reached nt only samples its last level; past nt it does nothing.
+template <int R>
+__global__ void __launch_bounds__(NTHREADS) batched_step_kernel(ShotDesc* shots,
+                                                                const BatchEntry* table,
+                                                                int nentries, int parity) {
+  const int b = remap_tile(blockIdx.x, nentries);
+  const BatchEntry e = table[b];
+  ShotDesc* sd = shots + e.shot;
+  const int n = sd->cnt[parity];
+  const int nt = sd->nt;
+  if (e.tile == 0 && threadIdx.x == 0) sd->cnt[parity ^ 1] = n <= nt ? n + 1 : n;
+  if (n > nt) return;
+  StepArgs a = sd->a;
+  a.cur = sd->buf[n & 1];
+  a.prev = sd->buf[(n + 1) & 1];
+  a.out = sd->buf[(n + 1) & 1];
+  if (sd->nsrc > 0 && n < nt) {
+    a.trace_row = sd->wavelet + (int64_t)n * sd->nsrc;
+  } else {
+    a.tile_beg = nullptr;
+    a.trace_row = nullptr;
+  }
+  a.samp_out = (n >= 1 && sd->nrec > 0) ? sd->traces + (int64_t)(n - 1) * sd->nrec : nullptr;
+  if (e.tile < 0) {
+    const int r = (-1 - e.tile) * NTHREADS + threadIdx.x;
+    if (a.samp_out != nullptr && r < a.nsamp)
+      a.samp_out[r] = sample_point<ST_F32>(a.cur, 1.f, a.samp_idx, a.samp_w, r);
+    return;
+  }
+  if (n < nt) step_tile<R, false, ST_F32, false>(a, e.tile, 1.f, 1.f, 1.f, 1.f);
+}
+
+// Copy each listed shot's counter cnt[0] into out (host read-back after a replay).
+__global__ void gather_counters_kernel(const ShotDesc* shots, const int* slots, int n, int* out) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) out[i] = shots[slots[i]].cnt[0];
+}
+
 template <int ST>
 __global__ void sample_kernel(const void* f, LevelMeta meta, int m, const int* idx,
                               const float* w, int n, float* out) {
@@ -609,6 +661,32 @@ hipError_t launch_step(const StepArgs& a, int r, bool grad, int st, bool diff, h
     case 8: return launch_variant<8>(a, grad, st, diff, s);
     default: return hipErrorInvalidValue;
   }
+}
+
+hipError_t launch_batched(ShotDesc* shots, const BatchEntry* table, int nentries, int r,
+                          int parity, hipStream_t s) {
+  if (nentries <= 0) return hipSuccess;
+  const dim3 grid(nentries), block(NTHREADS);
+  switch (r) {
+    case 1: hipLaunchKernelGGL(batched_step_kernel<1>, grid, block, 0, s, shots, table, nentries, parity); break;
+    case 2: hipLaunchKernelGGL(batched_step_kernel<2>, grid, block, 0, s, shots, table, nentries, parity); break;
+    case 3: hipLaunchKernelGGL(batched_step_kernel<3>, grid, block, 0, s, shots, table, nentries, parity); break;
+    case 4: hipLaunchKernelGGL(batched_step_kernel<4>, grid, block, 0, s, shots, table, nentries, parity); break;
+    case 5: hipLaunchKernelGGL(batched_step_kernel<5>, grid, block, 0, s, shots, table, nentries, parity); break;
+    case 6: hipLaunchKernelGGL(batched_step_kernel<6>, grid, block, 0, s, shots, table, nentries, parity); break;
+    case 7: hipLaunchKernelGGL(batched_step_kernel<7>, grid, block, 0, s, shots, table, nentries, parity); break;
+    case 8: hipLaunchKernelGGL(batched_step_kernel<8>, grid, block, 0, s, shots, table, nentries, parity); break;
+    default: return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
+}
+
+hipError_t launch_gather_counters(const ShotDesc* shots, const int* slots, int n, int* out,
+                                  hipStream_t s) {
+  if (n <= 0) return hipSuccess;
+  hipLaunchKernelGGL(gather_counters_kernel, dim3((n + 255) / 256), dim3(256), 0, s, shots, slots,
+                     n, out);
+  return hipGetLastError();
 }
 
 hipError_t launch_sample(const void* field, int st, LevelMeta meta, int m, const int* idx,

@@ -1,0 +1,108 @@
+"""Continuous-batching engine on the GPU: results alone vs in the mix (bitwise), against
+wave_forward (bitwise: same tile function) and the FP64 oracle, admission under a
+tight memory budget, and overlap of requests arriving while others run."""
+import time
+
+import numpy as np
+import pytest
+
+import oracle
+from helpers import rel_l2
+from paper_1912_00695_amd import inputs
+
+pytestmark = pytest.mark.gpu
+
+
+def _small_mix(seed=0, count=6):
+    from paper_1912_00695_amd import serving
+    rng = np.random.default_rng(seed)
+    shapes = [(64, 64, 64), (96, 80, 72), (70, 50, 90), (128, 64, 48)]
+    # sources at depth 24.5 cells, near the receiver line at z = 20
+    return [serving.mixed_request(rng, shapes=shapes, nt_range=(60, 160), nbl=8, src_z=24.5)
+            for _ in range(count)]
+
+
+def _engine(budget=8 << 30, slots=32):
+    from paper_1912_00695_amd import serving
+    return serving.Engine(budget, slots)
+
+
+def test_alone_equals_mix_equals_forward():
+    import torch
+    from paper_1912_00695_amd import wave
+    reqs = _small_mix()
+    with _engine() as eng:
+        mix = [eng.submit(r["grid"], r["vel"], r["wavelet"], r["src"], r["rec"]) for r in reqs]
+        eng.drain(120)
+        st = eng.stats()
+        print("mix stats", st, flush=True)
+        assert st["completed"] == len(reqs) and st["max_resident"] >= 2
+        alone = []
+        for r in reqs:
+            alone.append(eng.submit(r["grid"], r["vel"], r["wavelet"], r["src"], r["rec"]))
+            eng.drain(120)
+        for (i1, o1), (i2, o2) in zip(mix, alone):
+            assert eng.poll(i1)[0] == 0 and eng.poll(i2)[0] == 0
+            assert np.abs(o1).max() > 0
+            assert np.array_equal(o1, o2)
+    dev = torch.device("cuda:0")
+    for r, (_, o) in zip(reqs, mix):
+        f = wave.forward(r["grid"], torch.from_numpy(r["vel"]).to(dev),
+                         torch.from_numpy(r["wavelet"]).to(dev), r["src"], r["rec"])["rec"]
+        assert np.array_equal(f.cpu().numpy(), o)
+
+
+def test_engine_matches_oracle():
+    reqs = _small_mix(seed=3, count=2)
+    with _engine() as eng:
+        outs = [eng.submit(r["grid"], r["vel"], r["wavelet"], r["src"], r["rec"]) for r in reqs]
+        eng.drain(120)
+    for r, (_, o) in zip(reqs, outs):
+        g = r["grid"]
+        og = oracle.Grid((g.nx, g.ny, g.nz), (g.hx, g.hy, g.hz), g.so, g.dt, g.nt,
+                         nbl=tuple(g.nbl), vmax=g.vmax)
+        orec, _, _ = oracle.forward(og, r["vel"], r["wavelet"], r["src"], r["rec"])
+        print("engine vs oracle traces", rel_l2(o, orec), flush=True)
+        assert rel_l2(o, orec) <= 1e-5
+
+
+def test_budget_pressure_and_rejection():
+    from paper_1912_00695_amd import serving, wave
+    reqs = _small_mix(seed=7, count=6)
+    need = [serving.request_bytes(r["grid"], 1, len(r["rec"])) for r in reqs]
+    budget = sorted(need)[-1] + sorted(need)[-2]  # at most about two resident at once
+    with _engine(budget=budget, slots=8) as eng:
+        outs = [eng.submit(r["grid"], r["vel"], r["wavelet"], r["src"], r["rec"]) for r in reqs]
+        eng.drain(300)
+        st = eng.stats()
+        print("budget", budget, "stats", st, flush=True)
+        assert st["completed"] == 6 and st["max_pool_bytes"] <= budget
+        assert st["max_resident"] <= 3
+        big = serving.mixed_request(np.random.default_rng(1), shapes=[(256, 256, 256)])
+        with pytest.raises(wave.WaveError) as ei:
+            eng.submit(big["grid"], big["vel"], big["wavelet"], big["src"], big["rec"])
+        assert ei.value.status == wave.EBUSY
+        assert eng.stats()["rejected"] == 1
+    with _engine() as ref:
+        routs = [ref.submit(r["grid"], r["vel"], r["wavelet"], r["src"], r["rec"]) for r in reqs]
+        ref.drain(120)
+    for (_, a), (_, b) in zip(outs, routs):
+        assert np.array_equal(a, b)
+
+
+def test_continuous_arrivals_overlap():
+    """Requests arriving while others run are admitted and run concurrently."""
+    from paper_1912_00695_amd import serving
+    with _engine() as eng:
+        rng = np.random.default_rng(11)
+        make = lambda r: serving.mixed_request(r, shapes=[(96, 96, 96), (128, 128, 128)],
+                                               nt_range=(200, 400), nbl=10)
+        stats, recs = serving.run_poisson(eng, 24, 60.0, seed=5, make=make)
+        print("poisson stats", stats, flush=True)
+        assert all(r["status"] == 0 for r in recs)
+        assert stats["completed"] == 24 and stats["max_resident"] >= 2
+        # some request was admitted while an earlier one was still running
+        recs.sort(key=lambda r: r["t_admit"])
+        overlap = any(b["t_admit"] < a["t_done"] for a, b in zip(recs, recs[1:]))
+        assert overlap
+        assert 0 < stats["p50_latency_s"] <= stats["p99_latency_s"]
