@@ -13,9 +13,10 @@
 //     replayed; per-shot step counters live in device memory, so one graph serves
 //     any mix of shots at any step, and is re-captured only when the set of
 //     resident shots changes;
-//   * after each replay the worker reads the counters back, retires finished
-//     shots (traces copied to the caller's host buffer, pool space freed,
-//     latency recorded) and admits more.
+//   * the graph is launched several times back to back (about kSyncWork of
+//     estimated GPU time) before the worker reads the counters back, retires
+//     finished shots (traces copied to the caller's host buffer, pool space
+//     freed, latency recorded) and admits more.
 // Every shot's arithmetic is the single-shot kernel's (shared tile function), so
 // a result does not depend on the batch it ran in.
 #include <hip/hip_runtime.h>
@@ -39,7 +40,9 @@
 namespace wave {
 namespace {
 
-constexpr int kReplaySteps = 8;  // launches per space order in one graph replay (even)
+constexpr int kReplaySteps = 16;    // launches per space order in one captured graph (even)
+constexpr double kSyncWork = 2e-3;  // GPU seconds of work enqueued between host syncs
+constexpr double kUpdateRate = 250e9;  // grid-point updates per second, for that estimate
 
 double now_s() {
   using namespace std::chrono;
@@ -331,8 +334,14 @@ class Engine {
         }
         dirty = false;
       }
-      // one replay, then read back the counters
-      if (hipGraphLaunch(gexec_, s_exec_) != hipSuccess ||
+      // a few replays back to back, then read back the counters
+      double pts = 0;
+      for (Shot* s : active) pts += (double)s->g.nx * s->g.ny * s->g.nz;
+      const double step_s = std::max(2e-6, pts / kUpdateRate);
+      const int reps = std::max(1, std::min(64, (int)(kSyncWork / (kReplaySteps * step_s))));
+      bool launched = true;
+      for (int k = 0; k < reps && launched; ++k) launched = hipGraphLaunch(gexec_, s_exec_) == hipSuccess;
+      if (!launched ||
           launch_gather_counters(d_desc_, d_slots_, (int)active.size(), d_counts_, s_exec_) !=
               hipSuccess ||
           hipMemcpyAsync(h_counts_, d_counts_, sizeof(int) * active.size(),
