@@ -6,8 +6,10 @@
 //     it (a request that can never fit the budget is rejected with WAVE_EBUSY);
 //   * the worker admits queued requests first-come first-served, skipping ahead to
 //     later ones that fit when the head does not, whenever a slot and pool space
-//     are free; admission uploads the inputs and builds the shot's tables on an
-//     upload stream while resident shots keep running;
+//     are free; an uploader thread then copies the inputs and builds the shot's
+//     tables on an upload stream while resident shots keep running (host-pageable
+//     copies block the calling thread, so they stay off the thread that feeds
+//     the GPU);
 //   * resident shots of each space order advance together: a captured graph of
 //     kReplaySteps launches of the batched step kernel per space order is
 //     replayed; per-shot step counters live in device memory, so one graph serves
@@ -22,6 +24,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <atomic>
 #include <chrono>
 #include <condition_variable>
 #include <cstring>
@@ -88,7 +91,7 @@ class PoolAlloc {
   std::map<size_t, size_t> free_;  // offset -> length
 };
 
-enum ShotState { QUEUED = 0, UPLOADING = 1, ACTIVE = 2, DONE = 3, FAILED = 4 };
+enum ShotState { QUEUED = 0, ADMITTED = 5, UPLOADING = 1, ACTIVE = 2, DONE = 3, FAILED = 4 };
 
 struct Shot {
   uint64_t id = 0;
@@ -106,7 +109,7 @@ struct Shot {
   std::unique_ptr<Blob> blob;
   ShotDesc desc{};
   hipEvent_t ready = nullptr;
-  int state = QUEUED;
+  std::atomic<int> state{QUEUED};
   int counter = 0;
   int status = WAVE_EAGAIN;
   double t_submit = 0, t_admit = 0, t_done = 0;
@@ -135,6 +138,7 @@ class Engine {
     HIP_TRY(hipStreamCreateWithFlags(&s_up_, hipStreamNonBlocking));
     slot_used_.assign(max_slots_, 0);
     worker_ = std::thread([this] { loop(); });
+    uploader_ = std::thread([this] { upload_loop(); });
     return WAVE_OK;
   }
 
@@ -143,8 +147,14 @@ class Engine {
       std::lock_guard<std::mutex> lk(mu_);
       stop_ = true;
     }
+    {
+      std::lock_guard<std::mutex> lk(up_mu_);
+      stop_up_ = true;
+    }
     cv_.notify_all();
+    up_cv_.notify_all();
     if (worker_.joinable()) worker_.join();
+    if (uploader_.joinable()) uploader_.join();
     (void)hipSetDevice(device_);
     if (s_exec_) (void)hipStreamSynchronize(s_exec_);
     if (s_up_) (void)hipStreamSynchronize(s_up_);
@@ -303,16 +313,28 @@ class Engine {
           it = queue_.erase(it);
         }
       }
-      for (Shot* s : incoming) {
-        if (start_upload(s) != WAVE_OK) {
-          fail(s);
-          continue;
+      if (!incoming.empty()) {
+        for (Shot* s : incoming) {
+          s->state = ADMITTED;
+          resident.push_back(s);
         }
-        resident.push_back(s);
+        {
+          std::lock_guard<std::mutex> lk(up_mu_);
+          for (Shot* s : incoming) upload_q_.push_back(s);
+        }
+        up_cv_.notify_all();
+      }
+      // drop shots whose upload failed
+      {
+        std::vector<Shot*> keep;
+        for (Shot* s : resident)
+          if (s->state != FAILED) keep.push_back(s);
+        resident.swap(keep);
       }
       // promote finished uploads
       for (Shot* s : resident)
-        if (s->state == UPLOADING && hipEventQuery(s->ready) == hipSuccess) {
+        if (s->state.load(std::memory_order_acquire) == UPLOADING &&
+            hipEventQuery(s->ready) == hipSuccess) {
           s->state = ACTIVE;
           s->blob.reset();
           std::vector<float>().swap(s->vel);
@@ -372,6 +394,28 @@ class Engine {
     }
   }
 
+  // Uploader thread: runs start_upload for admitted shots in admission order.
+  void upload_loop() {
+    (void)hipSetDevice(device_);
+    while (true) {
+      Shot* s = nullptr;
+      {
+        std::unique_lock<std::mutex> lk(up_mu_);
+        up_cv_.wait_for(lk, std::chrono::milliseconds(5),
+                        [this] { return stop_up_ || !upload_q_.empty(); });
+        if (stop_up_) return;
+        if (upload_q_.empty()) {
+          std::lock_guard<std::mutex> lk2(mu_);
+          if (stop_) return;
+          continue;
+        }
+        s = upload_q_.front();
+        upload_q_.pop_front();
+      }
+      if (start_upload(s) != WAVE_OK) fail(s);
+    }
+  }
+
   int free_slot() const {
     for (int i = 0; i < max_slots_; ++i)
       if (!slot_used_[i]) return i;
@@ -422,7 +466,7 @@ class Engine {
                            s_up_));
     HIP_TRY(hipEventCreateWithFlags(&s->ready, hipEventDisableTiming));
     HIP_TRY(hipEventRecord(s->ready, s_up_));
-    s->state = UPLOADING;
+    s->state.store(UPLOADING, std::memory_order_release);
     return WAVE_OK;
   }
 
@@ -530,8 +574,11 @@ class Engine {
   hipStream_t s_exec_ = nullptr, s_up_ = nullptr;
   hipGraphExec_t gexec_ = nullptr;
   std::vector<char> slot_used_;
-  std::thread worker_;
-  std::mutex mu_;
+  std::thread worker_, uploader_;
+  std::mutex mu_, up_mu_;
+  std::condition_variable up_cv_;
+  std::deque<Shot*> upload_q_;
+  bool stop_up_ = false;
   std::condition_variable cv_, done_cv_;
   bool stop_ = false;
   std::deque<Shot*> queue_;
