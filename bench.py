@@ -291,7 +291,7 @@ def main():
         return
     if not args.no_sweep:
         sweep = {}
-        for so in (2, 4, 8, 12, 16):
+        for so in (2, 4, 8, 12, 16, 24):
             S = Solver(c2_problem(so), dev)
             e, _ = time_solves(S, 3, 1)
             g = npts * 500 * 3 / e / 1e9

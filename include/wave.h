@@ -13,7 +13,7 @@
  *     u^{n+1} = ( 2u^n - (1-b) u^{n-1} + dt^2 v^2 ( L_h u^n + P^T s^n ) ) / (1+b)
  *     b = dt gamma / 2,     d^n = R u^{n+1}
  *
- * L_h: star Laplacian of even space order SO = 2r (2..16), weights of the centred
+ * L_h: star Laplacian of even space order SO = 2r (2..24), weights of the centred
  * second-derivative stencil, values outside the grid are zero (an r-wide zero
  * halo). gamma = gamma_x(i) + gamma_y(j) + gamma_z(k); on a face of width nbl the
  * d-th point from the outside (d = 0..nbl-1) has p = (nbl-d)/nbl and
@@ -79,7 +79,7 @@ extern "C" {
 typedef struct {
   int32_t nx, ny, nz;  /* grid points per axis, sponge included                       */
   double hx, hy, hz;   /* spacing [m]                                                 */
-  int32_t so;          /* space order, even, 2..16 (stencil radius so/2)              */
+  int32_t so;          /* space order, even, 2..24 (stencil radius so/2)              */
   double dt;           /* time step [s], at most wave_cfl_dt_max(so, vmax, hx, hy, hz) */
   int32_t nt;          /* number of time steps (>= 0)                                 */
   int32_t nbl[6];      /* sponge width per face: x-, x+, y-, y+, z-, z+ (0 = none)    */

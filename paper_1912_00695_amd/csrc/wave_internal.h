@@ -15,7 +15,7 @@ constexpr int TY = 16;
 constexpr int VX = 4;
 constexpr int NTX = TX / VX;     // threads along x
 constexpr int NTHREADS = NTX * TY;
-constexpr int MAXR = 8;          // SO <= 16
+constexpr int MAXR = 12;         // SO <= 24
 constexpr int SAMPLE_THREADS = 256;
 
 // Pitched field geometry: rows padded to a multiple of 32 floats (128 bytes);

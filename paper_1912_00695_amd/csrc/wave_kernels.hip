@@ -137,7 +137,7 @@ template <int R, bool GRAD, int ST, bool DIFF>
 __device__ __forceinline__ void step_tile(const StepArgs& a, const int t, const float dec_c,
                                           const float dec_p, const float enc_u,
                                           const float enc_d) {
-  constexpr int XH = R <= 4 ? 4 : 8;  // x-halo width in floats (multiple of 4)
+  constexpr int XH = R <= 4 ? 4 : (R <= 8 ? 8 : 12);  // x-halo width (multiple of 4)
   constexpr int XH4 = XH / 4;
   constexpr int LROW4 = NTX + 2 * XH4;  // float4 per LDS row
   constexpr int LROWS = TY + 2 * R;
@@ -659,6 +659,10 @@ hipError_t launch_step(const StepArgs& a, int r, bool grad, int st, bool diff, h
     case 6: return launch_variant<6>(a, grad, st, diff, s);
     case 7: return launch_variant<7>(a, grad, st, diff, s);
     case 8: return launch_variant<8>(a, grad, st, diff, s);
+    case 9: return launch_variant<9>(a, grad, st, diff, s);
+    case 10: return launch_variant<10>(a, grad, st, diff, s);
+    case 11: return launch_variant<11>(a, grad, st, diff, s);
+    case 12: return launch_variant<12>(a, grad, st, diff, s);
     default: return hipErrorInvalidValue;
   }
 }
@@ -676,6 +680,10 @@ hipError_t launch_batched(ShotDesc* shots, const BatchEntry* table, int nentries
     case 6: hipLaunchKernelGGL(batched_step_kernel<6>, grid, block, 0, s, shots, table, nentries, parity); break;
     case 7: hipLaunchKernelGGL(batched_step_kernel<7>, grid, block, 0, s, shots, table, nentries, parity); break;
     case 8: hipLaunchKernelGGL(batched_step_kernel<8>, grid, block, 0, s, shots, table, nentries, parity); break;
+    case 9: hipLaunchKernelGGL(batched_step_kernel<9>, grid, block, 0, s, shots, table, nentries, parity); break;
+    case 10: hipLaunchKernelGGL(batched_step_kernel<10>, grid, block, 0, s, shots, table, nentries, parity); break;
+    case 11: hipLaunchKernelGGL(batched_step_kernel<11>, grid, block, 0, s, shots, table, nentries, parity); break;
+    case 12: hipLaunchKernelGGL(batched_step_kernel<12>, grid, block, 0, s, shots, table, nentries, parity); break;
     default: return hipErrorInvalidValue;
   }
   return hipGetLastError();

@@ -49,7 +49,7 @@ def test_c1_plain_forward():
     assert err <= TOL
 
 
-@pytest.mark.parametrize("so", [2, 4, 6, 8, 10, 12, 14, 16])
+@pytest.mark.parametrize("so", [2, 4, 6, 8, 10, 12, 14, 16, 18, 20, 22, 24])
 def test_ragged_multitile(so):
     case = ragged_case(so)
     _oracle_inputs(case)
@@ -61,7 +61,7 @@ def test_ragged_multitile(so):
     assert e_u <= TOL and e_r <= TOL
 
 
-@pytest.mark.parametrize("so", [2, 4, 8, 12, 16])
+@pytest.mark.parametrize("so", [2, 4, 8, 12, 16, 24])
 def test_c2_reduced_grid(so):
     case = c2_case(so, nt=120, n=(96, 80, 72))
     print("case C2-reduced", case.n, "SO", so, flush=True)
@@ -87,7 +87,7 @@ def test_c2_full_size_so8_short():
     assert e_u <= TOL and e_r <= TOL
 
 
-@pytest.mark.parametrize("so", [4, 8, 16])
+@pytest.mark.parametrize("so", [4, 8, 16, 24])
 def test_c2_full_length(so):
     """The full benchmark problem (256^3, 500 steps, launch configuration of the
     benchmark) against the oracle; a second receiver line near the source gives

@@ -59,7 +59,7 @@ def test_so2_weights_match_paper_listing():
     assert centre == 3 * w[0]
 
 
-@pytest.mark.parametrize("so", [2, 4, 8, 12, 16])
+@pytest.mark.parametrize("so", [2, 4, 8, 12, 16, 24])
 @pytest.mark.parametrize("h", [(10.0, 10.0, 10.0), (5.0, 10.0, 20.0)])
 def test_cfl_matches_symbol_maximum(so, h):
     # dt_max = 2 / (v sqrt(max_k symbol)), the symbol sum_a h_a^-2 (-w0 - 2 sum_q w_q cos(q k h_a))
