@@ -39,6 +39,7 @@
 #include "../../include/wave.h"
 #include "wave_host.h"
 #include "wave_internal.h"
+#include "wave_sched.h"
 
 namespace wave {
 namespace {
@@ -52,44 +53,7 @@ double now_s() {
   return duration<double>(steady_clock::now().time_since_epoch()).count();
 }
 
-// First-fit allocator over [0, size) with 256-byte granularity (host bookkeeping
-// of the device pool).
-class PoolAlloc {
- public:
-  explicit PoolAlloc(size_t size) { free_[0] = size; }
-  bool alloc(size_t bytes, size_t* off) {
-    bytes = align_up(bytes);
-    for (auto it = free_.begin(); it != free_.end(); ++it) {
-      if (it->second >= bytes) {
-        *off = it->first;
-        const size_t rest = it->second - bytes, base = it->first + bytes;
-        free_.erase(it);
-        if (rest) free_[base] = rest;
-        return true;
-      }
-    }
-    return false;
-  }
-  void release(size_t off, size_t bytes) {
-    bytes = align_up(bytes);
-    auto it = free_.emplace(off, bytes).first;
-    auto nx = std::next(it);
-    if (nx != free_.end() && it->first + it->second == nx->first) {
-      it->second += nx->second;
-      free_.erase(nx);
-    }
-    if (it != free_.begin()) {
-      auto pv = std::prev(it);
-      if (pv->first + pv->second == it->first) {
-        pv->second += it->second;
-        free_.erase(it);
-      }
-    }
-  }
-
- private:
-  std::map<size_t, size_t> free_;  // offset -> length
-};
+using sched::PoolAlloc;
 
 enum ShotState { QUEUED = 0, ADMITTED = 5, UPLOADING = 1, ACTIVE = 2, DONE = 3, FAILED = 4 };
 
@@ -241,18 +205,15 @@ class Engine {
     st->queued = queue_.size();
     st->resident = resident_;
     if (!lat_.empty()) {
-      std::vector<double> v = lat_;
-      std::sort(v.begin(), v.end());
-      auto rank = [&](double q) {  // nearest-rank percentile
-        size_t k = (size_t)std::ceil(q * v.size());
-        return v[std::min(v.size(), std::max<size_t>(k, 1)) - 1];
-      };
-      st->p50_latency_s = rank(0.50);
-      st->p99_latency_s = rank(0.99);
-      double sum = 0;
-      for (double x : v) sum += x;
-      st->mean_latency_s = sum / v.size();
-      st->max_latency_s = v.back();
+      st->p50_latency_s = sched::percentile(lat_, 0.50);
+      st->p99_latency_s = sched::percentile(lat_, 0.99);
+      double sum = 0, mx = 0;
+      for (double x : lat_) {
+        sum += x;
+        mx = std::max(mx, x);
+      }
+      st->mean_latency_s = sum / lat_.size();
+      st->max_latency_s = mx;
     }
     st->total_gpt = total_updates_ / 1e9;
     st->busy_s = busy_s_;
@@ -291,16 +252,15 @@ class Engine {
           continue;
         }
         // admission: FIFO with skip-ahead over requests that fit
-        for (auto it = queue_.begin(); it != queue_.end();) {
-          Shot* s = *it;
-          int slot = free_slot();
-          size_t off = 0;
-          if (slot < 0) break;
-          if (!alloc_.alloc(s->bytes, &off)) {
-            ++it;
-            continue;
-          }
-          s->off = off;
+        int nfree = 0;
+        for (int i = 0; i < max_slots_; ++i) nfree += slot_used_[i] ? 0 : 1;
+        std::vector<size_t> qb;
+        for (Shot* s : queue_) qb.push_back(s->bytes);
+        const std::vector<sched::Admission> adm = sched::admit(qb, alloc_, nfree);
+        for (const sched::Admission& ad : adm) {
+          Shot* s = queue_[ad.pos];
+          const int slot = free_slot();
+          s->off = ad.off;
           s->slot = slot;
           slot_used_[slot] = 1;
           pool_used_ += align_up(s->bytes);
@@ -310,8 +270,8 @@ class Engine {
           max_resident_ = std::max<uint64_t>(max_resident_, resident_);
           s->t_admit = now_s();
           incoming.push_back(s);
-          it = queue_.erase(it);
         }
+        for (size_t k = adm.size(); k-- > 0;) queue_.erase(queue_.begin() + adm[k].pos);
       }
       if (!incoming.empty()) {
         for (Shot* s : incoming) {
