@@ -48,6 +48,7 @@ struct Ctx {
   Layout L;
   char* ws;
   hipStream_t s;
+  bool nt;  // streamed arrays bypass the caches (working set above the Infinity Cache)
   double wx[MAXR + 1], wy[MAXR + 1], wz[MAXR + 1], wc;
   template <class T>
   T* at(size_t off) const { return reinterpret_cast<T*>(ws + off); }

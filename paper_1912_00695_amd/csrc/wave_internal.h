@@ -109,8 +109,10 @@ struct BatchEntry {
 };
 
 // Launchers (wave_kernels.hip). All return hipGetLastError() after the launch.
-// st: StoreKind; diff: difference-form storage (reduced precision only).
-hipError_t launch_step(const StepArgs& a, int r, bool grad, int st, bool diff, hipStream_t s);
+// st: StoreKind; diff: difference-form storage (reduced precision only); nt:
+// non-temporal loads/stores of the streamed arrays (prev, c2, out).
+hipError_t launch_step(const StepArgs& a, int r, bool grad, int st, bool diff, bool nt,
+                       hipStream_t s);
 // one batched step of every shot in table (space-order radius r, launch parity)
 hipError_t launch_batched(ShotDesc* shots, const BatchEntry* table, int nentries, int r,
                           int parity, hipStream_t s);

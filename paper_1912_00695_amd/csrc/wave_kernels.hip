@@ -50,29 +50,49 @@ __device__ __forceinline__ int remap_tile(int b, int nb) {
 // Wavefield element access per storage kind: 4 consecutive values (16-byte or
 // 8-byte aligned) or 1 value, widened to / narrowed from FP32 (round to nearest
 // even).
+// Element access per storage kind: 4 consecutive values (16- or 8-byte aligned)
+// or 1 value, widened to / narrowed from FP32 (round to nearest even). NT selects
+// non-temporal loads/stores (streamed once per step, not kept in the caches).
+typedef float f4v __attribute__((ext_vector_type(4)));
+typedef _Float16 h4v __attribute__((ext_vector_type(4)));
+typedef unsigned u2v __attribute__((ext_vector_type(2)));
+template <bool NT, class V>
+__device__ __forceinline__ V vload(const V* p) {
+  if constexpr (NT) return __builtin_nontemporal_load(p); else return *p;
+}
+template <bool NT, class V>
+__device__ __forceinline__ void vstore(V* p, const V& v) {
+  if constexpr (NT) __builtin_nontemporal_store(v, p); else *p = v;
+}
 template <int ST> struct Store;
 template <> struct Store<ST_F32> {
+  template <bool NT = false>
   __device__ static float4 ld(const void* b, int64_t i) {
-    return ld4(static_cast<const float*>(b) + i);
+    const f4v v = vload<NT>(reinterpret_cast<const f4v*>(static_cast<const float*>(b) + i));
+    return make_float4(v.x, v.y, v.z, v.w);
   }
   __device__ static float ld1(const void* b, int64_t i) { return static_cast<const float*>(b)[i]; }
+  template <bool NT = false>
   __device__ static void st(void* b, int64_t i, const float4& v) {
-    st4(static_cast<float*>(b) + i, v);
+    f4v w;
+    w.x = v.x; w.y = v.y; w.z = v.z; w.w = v.w;
+    vstore<NT>(reinterpret_cast<f4v*>(static_cast<float*>(b) + i), w);
   }
 };
-typedef _Float16 h4v __attribute__((ext_vector_type(4)));
 template <> struct Store<ST_F16> {
+  template <bool NT = false>
   __device__ static float4 ld(const void* b, int64_t i) {
-    const h4v h = *reinterpret_cast<const h4v*>(static_cast<const _Float16*>(b) + i);
+    const h4v h = vload<NT>(reinterpret_cast<const h4v*>(static_cast<const _Float16*>(b) + i));
     return make_float4((float)h.x, (float)h.y, (float)h.z, (float)h.w);
   }
   __device__ static float ld1(const void* b, int64_t i) {
     return (float)static_cast<const _Float16*>(b)[i];
   }
+  template <bool NT = false>
   __device__ static void st(void* b, int64_t i, const float4& v) {
     h4v h;
     h.x = (_Float16)v.x; h.y = (_Float16)v.y; h.z = (_Float16)v.z; h.w = (_Float16)v.w;
-    *reinterpret_cast<h4v*>(static_cast<_Float16*>(b) + i) = h;
+    vstore<NT>(reinterpret_cast<h4v*>(static_cast<_Float16*>(b) + i), h);
   }
 };
 __device__ __forceinline__ unsigned bf16_rne(float f) {
@@ -80,19 +100,22 @@ __device__ __forceinline__ unsigned bf16_rne(float f) {
   return (u + 0x7fffu + ((u >> 16) & 1u)) >> 16;
 }
 template <> struct Store<ST_BF16> {
+  template <bool NT = false>
   __device__ static float4 ld(const void* b, int64_t i) {
-    const uint2 r = *reinterpret_cast<const uint2*>(static_cast<const unsigned short*>(b) + i);
+    const u2v r =
+        vload<NT>(reinterpret_cast<const u2v*>(static_cast<const unsigned short*>(b) + i));
     return make_float4(__uint_as_float(r.x << 16), __uint_as_float(r.x & 0xffff0000u),
                        __uint_as_float(r.y << 16), __uint_as_float(r.y & 0xffff0000u));
   }
   __device__ static float ld1(const void* b, int64_t i) {
     return __uint_as_float((unsigned)static_cast<const unsigned short*>(b)[i] << 16);
   }
+  template <bool NT = false>
   __device__ static void st(void* b, int64_t i, const float4& v) {
-    uint2 r;
+    u2v r;
     r.x = bf16_rne(v.x) | (bf16_rne(v.y) << 16);
     r.y = bf16_rne(v.z) | (bf16_rne(v.w) << 16);
-    *reinterpret_cast<uint2*>(static_cast<unsigned short*>(b) + i) = r;
+    vstore<NT>(reinterpret_cast<u2v*>(static_cast<unsigned short*>(b) + i), r);
   }
 };
 
@@ -133,7 +156,7 @@ __device__ __forceinline__ float sample_point(const void* f, float dec, const in
 // One tile of one step: the z-sweep of a TX x TY column block over one z-chunk.
 // Shared by the single-shot kernel and the batched serving kernel, so a shot's
 // values do not depend on what else is in the launch.
-template <int R, bool GRAD, int ST, bool DIFF>
+template <int R, bool GRAD, int ST, bool DIFF, bool NT>
 __device__ __forceinline__ void step_tile(const StepArgs& a, const int t, const float dec_c,
                                           const float dec_p, const float enc_u,
                                           const float enc_d) {
@@ -162,11 +185,11 @@ __device__ __forceinline__ void step_tile(const StepArgs& a, const int t, const 
   const int col = y * a.g.pitch + x0;
   const float4 zero4 = make_float4(0.f, 0.f, 0.f, 0.f);
   auto ldc = [&](int64_t i) {
-    const float4 v = Store<ST>::ld(a.cur, i);
+    const float4 v = Store<ST>::template ld<false>(a.cur, i);
     if constexpr (ST == ST_F32) return v; else return mul4(v, dec_c);
   };
   auto ldp = [&](int64_t i) {
-    const float4 v = Store<ST>::ld(a.prev, i);
+    const float4 v = Store<ST>::template ld<NT>(a.prev, i);
     if constexpr (ST == ST_F32) return v; else return mul4(v, dec_p);
   };
   float mx_u = 0.f, mx_d = 0.f;  // running maxima of the written level (reduced precision)
@@ -222,7 +245,7 @@ __device__ __forceinline__ void step_tile(const StepArgs& a, const int t, const 
   }
   inj[tid] = zero4;
   float4 up = colok ? ldp(z0 * plane + col) : zero4;
-  float4 cc = colok ? ld4(a.c2 + z0 * plane + col) : zero4;
+  float4 cc = colok ? Store<ST_F32>::template ld<NT>(a.c2, z0 * plane + col) : zero4;
   __syncthreads();
 
   int e = 0, e_end = 0;
@@ -245,7 +268,7 @@ __device__ __forceinline__ void step_tile(const StepArgs& a, const int t, const 
         nhv[k] = (hok[k] && more) ? ldc((z + 1) * plane + hoff[k]) : zero4;
       if (colok && more) {
         nup = ldp((z + 1) * plane + col);
-        ncc = ld4(a.c2 + (z + 1) * plane + col);
+        ncc = Store<ST_F32>::template ld<NT>(a.c2, (z + 1) * plane + col);
       }
     }
 
@@ -334,15 +357,15 @@ __device__ __forceinline__ void step_tile(const StepArgs& a, const int t, const 
     if (colok) {
       const int64_t at = z * plane + col;
       if constexpr (ST == ST_F32) {
-        Store<ST>::st(a.out, at, o);
+        Store<ST>::template st<NT>(a.out, at, o);
       } else {
         mx_u = fmaxf(mx_u, fmaxf(fmaxf(fabsf(o.x), fabsf(o.y)), fmaxf(fabsf(o.z), fabsf(o.w))));
         if constexpr (DIFF) {
           mx_d = fmaxf(mx_d, fmaxf(fmaxf(fabsf(dn.x), fabsf(dn.y)), fmaxf(fabsf(dn.z), fabsf(dn.w))));
-          Store<ST>::st(a.out_u, at, mul4(o, enc_u));
-          Store<ST>::st(a.out, at, mul4(dn, enc_d));
+          Store<ST>::template st<NT>(a.out_u, at, mul4(o, enc_u));
+          Store<ST>::template st<NT>(a.out, at, mul4(dn, enc_d));
         } else {
-          Store<ST>::st(a.out, at, mul4(o, enc_u));
+          Store<ST>::template st<NT>(a.out, at, mul4(o, enc_u));
         }
       }
       if constexpr (GRAD) {
@@ -380,7 +403,7 @@ __device__ __forceinline__ void step_tile(const StepArgs& a, const int t, const 
   }
 }
 
-template <int R, bool GRAD, int ST, bool DIFF>
+template <int R, bool GRAD, int ST, bool DIFF, bool NT>
 __global__ void __launch_bounds__(NTHREADS) step_kernel(const StepArgs a) {
   // Per-level scales of reduced-precision storage: decode cur and prev, choose
   // the encode scales of the level written here from the previous maxima.
@@ -415,7 +438,7 @@ __global__ void __launch_bounds__(NTHREADS) step_kernel(const StepArgs a) {
     return;
   }
   const int t = a.xcd_remap ? remap_tile(bid, a.nstencil_blocks) : bid;
-  step_tile<R, GRAD, ST, DIFF>(a, t, dec_c, dec_p, enc_u, enc_d);
+  step_tile<R, GRAD, ST, DIFF, NT>(a, t, dec_c, dec_p, enc_u, enc_d);
 }
 
 // Serving: one launch advances every active shot of one space order by a step.
@@ -452,7 +475,7 @@ __global__ void __launch_bounds__(NTHREADS) batched_step_kernel(ShotDesc* shots,
       a.samp_out[r] = sample_point<ST_F32>(a.cur, 1.f, a.samp_idx, a.samp_w, r);
     return;
   }
-  if (n < nt) step_tile<R, false, ST_F32, false>(a, e.tile, 1.f, 1.f, 1.f, 1.f);
+  if (n < nt) step_tile<R, false, ST_F32, false, false>(a, e.tile, 1.f, 1.f, 1.f, 1.f);
 }
 
 // Copy each listed shot's counter cnt[0] into out (host read-back after a replay).
@@ -601,8 +624,8 @@ __global__ void encode_initial_kernel(const float* a, const float* b, void* ua, 
       va[k] = x;
       vb[k] = diff ? x - y : y;
     }
-    Store<ST>::st(ua, p, make_float4(va[0] * ea, va[1] * ea, va[2] * ea, va[3] * ea));
-    Store<ST>::st(ub, p, make_float4(vb[0] * eb, vb[1] * eb, vb[2] * eb, vb[3] * eb));
+    Store<ST>::template st<false>(ua, p, make_float4(va[0] * ea, va[1] * ea, va[2] * ea, va[3] * ea));
+    Store<ST>::template st<false>(ub, p, make_float4(vb[0] * eb, vb[1] * eb, vb[2] * eb, vb[3] * eb));
   }
 }
 
@@ -626,43 +649,51 @@ int elementwise_blocks(int64_t n) {
   return (int)b;
 }
 
-template <int R, bool GRAD, int ST, bool DIFF>
+template <int R, bool GRAD, int ST, bool DIFF, bool NT>
 hipError_t launch_r(const StepArgs& a, hipStream_t s) {
   const int nsamp_blocks = a.samp_out != nullptr ? (a.nsamp + NTHREADS - 1) / NTHREADS : 0;
   const dim3 grid(a.nstencil_blocks + nsamp_blocks), block(NTHREADS);
-  hipLaunchKernelGGL((step_kernel<R, GRAD, ST, DIFF>), grid, block, 0, s, a);
+  hipLaunchKernelGGL((step_kernel<R, GRAD, ST, DIFF, NT>), grid, block, 0, s, a);
   return hipGetLastError();
 }
 
+template <int R, int ST, bool DIFF>
+hipError_t launch_nt(const StepArgs& a, bool nt, hipStream_t s) {
+  return nt ? launch_r<R, false, ST, DIFF, true>(a, s) : launch_r<R, false, ST, DIFF, false>(a, s);
+}
+
 template <int R>
-hipError_t launch_variant(const StepArgs& a, bool grad, int st, bool diff, hipStream_t s) {
+hipError_t launch_variant(const StepArgs& a, bool grad, int st, bool diff, bool nt,
+                          hipStream_t s) {
   if (st == ST_F32) {
     if (diff) return hipErrorInvalidValue;
-    return grad ? launch_r<R, true, ST_F32, false>(a, s) : launch_r<R, false, ST_F32, false>(a, s);
+    return grad ? launch_r<R, true, ST_F32, false, false>(a, s)
+                : launch_nt<R, ST_F32, false>(a, nt, s);
   }
   if (grad) return hipErrorInvalidValue;
   if (st == ST_F16)
-    return diff ? launch_r<R, false, ST_F16, true>(a, s) : launch_r<R, false, ST_F16, false>(a, s);
+    return diff ? launch_nt<R, ST_F16, true>(a, nt, s) : launch_nt<R, ST_F16, false>(a, nt, s);
   if (st == ST_BF16)
-    return diff ? launch_r<R, false, ST_BF16, true>(a, s) : launch_r<R, false, ST_BF16, false>(a, s);
+    return diff ? launch_nt<R, ST_BF16, true>(a, nt, s) : launch_nt<R, ST_BF16, false>(a, nt, s);
   return hipErrorInvalidValue;
 }
 }  // namespace
 
-hipError_t launch_step(const StepArgs& a, int r, bool grad, int st, bool diff, hipStream_t s) {
+hipError_t launch_step(const StepArgs& a, int r, bool grad, int st, bool diff, bool nt,
+                       hipStream_t s) {
   switch (r) {
-    case 1: return launch_variant<1>(a, grad, st, diff, s);
-    case 2: return launch_variant<2>(a, grad, st, diff, s);
-    case 3: return launch_variant<3>(a, grad, st, diff, s);
-    case 4: return launch_variant<4>(a, grad, st, diff, s);
-    case 5: return launch_variant<5>(a, grad, st, diff, s);
-    case 6: return launch_variant<6>(a, grad, st, diff, s);
-    case 7: return launch_variant<7>(a, grad, st, diff, s);
-    case 8: return launch_variant<8>(a, grad, st, diff, s);
-    case 9: return launch_variant<9>(a, grad, st, diff, s);
-    case 10: return launch_variant<10>(a, grad, st, diff, s);
-    case 11: return launch_variant<11>(a, grad, st, diff, s);
-    case 12: return launch_variant<12>(a, grad, st, diff, s);
+    case 1: return launch_variant<1>(a, grad, st, diff, nt, s);
+    case 2: return launch_variant<2>(a, grad, st, diff, nt, s);
+    case 3: return launch_variant<3>(a, grad, st, diff, nt, s);
+    case 4: return launch_variant<4>(a, grad, st, diff, nt, s);
+    case 5: return launch_variant<5>(a, grad, st, diff, nt, s);
+    case 6: return launch_variant<6>(a, grad, st, diff, nt, s);
+    case 7: return launch_variant<7>(a, grad, st, diff, nt, s);
+    case 8: return launch_variant<8>(a, grad, st, diff, nt, s);
+    case 9: return launch_variant<9>(a, grad, st, diff, nt, s);
+    case 10: return launch_variant<10>(a, grad, st, diff, nt, s);
+    case 11: return launch_variant<11>(a, grad, st, diff, nt, s);
+    case 12: return launch_variant<12>(a, grad, st, diff, nt, s);
     default: return hipErrorInvalidValue;
   }
 }
