@@ -157,6 +157,20 @@ int wave_gradient(const wave_grid* g, const float* vel, const float* wavelet,
                   float* grad_vel, float* grad_wavelet, void* workspace, size_t ws_bytes,
                   void* hip_stream);
 
+/* Reverse-time-migration image (the imaging condition on the forward and the
+ * backward fields; the paper names RTM among the seismic inversion workloads
+ * in its introduction): the zero-lag cross-correlation
+ *   image = sum_{n=1..nt} u^n lambda^n
+ * of the forward field u (wavelet at the sources, zero initial state) with the
+ * backward field lambda of wave_adjoint driven by rec_data [nt][nrec] at the
+ * receivers (lambda^{nt} = 0). Forward levels come from ckpt / ckpt_every as in
+ * wave_gradient (NULL: internal forward pass); workspace as for
+ * WAVE_MODE_GRADIENT. image [nz][ny][nx] (device). FP32 storage only. */
+int wave_rtm(const wave_grid* g, const float* vel, const float* wavelet,
+             const double* src_xyz_h, int nsrc, const double* rec_xyz_h, int nrec,
+             const float* rec_data, const float* ckpt, int ckpt_every, float* image,
+             void* workspace, size_t ws_bytes, void* hip_stream);
+
 /* ---------------------------------------------------------------------------
  * Serving: continuous batching of independent forward shots on one GPU.
  *

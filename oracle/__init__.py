@@ -61,6 +61,9 @@ def lib():
         L.oracle_gradient.argtypes = [gp, dp, dp, dp, ctypes.c_int, dp, ctypes.c_int, dp,
                                       ctypes.c_int64, dp, dp, dp]
         L.oracle_gradient.restype = ctypes.c_int
+        L.oracle_gradient_image.argtypes = [gp, dp, dp, dp, ctypes.c_int, dp, ctypes.c_int, dp,
+                                            ctypes.c_int64, dp, dp, dp, dp]
+        L.oracle_gradient_image.restype = ctypes.c_int
         L.oracle_num_threads.argtypes = []
         L.oracle_num_threads.restype = ctypes.c_int
         _lib = L
@@ -224,6 +227,24 @@ def gradient(grid, vel, wavelet, src_xyz, rec_xyz, rec_grad, ckpt_every=0):
     if rc != 0:
         raise ValueError("oracle_gradient failed (%d)" % rc)
     return gm, gv, gw
+
+
+def rtm_image(grid, vel, wavelet, src_xyz, rec_xyz, rec_data, ckpt_every=0):
+    """Zero-lag cross-correlation image sum_{n=1..nt} u^n lambda^n of the forward field
+    (sources) with the adjoint field driven by rec_data at the receivers."""
+    vel = _d(vel, grid.shape)
+    src = _d(src_xyz).reshape(-1, 3)
+    rec = _d(rec_xyz).reshape(-1, 3)
+    ns, nr = src.shape[0], rec.shape[0]
+    wav = _d(wavelet).reshape(grid.nt, ns)
+    rd = _d(rec_data).reshape(grid.nt, nr)
+    img = np.zeros(grid.shape)
+    rc = lib().oracle_gradient_image(ctypes.byref(grid.c()), _p(vel), _p(wav), _p(src), ns,
+                                     _p(rec), nr, _p(rd), int(ckpt_every), None, None, None,
+                                     _p(img))
+    if rc != 0:
+        raise ValueError("oracle_gradient_image failed (%d)" % rc)
+    return img
 
 
 def num_threads():

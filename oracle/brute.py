@@ -162,3 +162,15 @@ def forward_matrix(n, h, so, dt, nt, vel, src_xyz, rec_xyz, nbl=(0,) * 6, vmax=1
     Rbig = np.kron(np.eye(nt), R)        # (nt nrec) x (nt N)
     del N
     return Rbig @ Tinv @ Pbig
+
+
+def adjoint_levels(n, h, so, dt, nt, vel, rec_xyz, rec_data, nbl=(0,) * 6, vmax=1500.0):
+    """Adjoint levels lambda^0..lambda^{nt-1} from the transposed space-time system of
+    the discrete PDE: T^T mu = (I (x) R^T) d, where row n of T is the equation that
+    produces u^{n+1} and receives P^T s^n, so F^T d = (I (x) P) mu and lambda^n = mu_n.
+    Returns [nt][N]."""
+    N = n[0] * n[1] * n[2]
+    T, _ = system(n, h, so, dt, nt, vel, nbl, vmax)
+    R = interp_matrix(n, h, rec_xyz)
+    rhs = (np.asarray(rec_data, dtype=np.float64).reshape(nt, -1) @ R).ravel()
+    return np.linalg.solve(T.T, rhs).reshape(nt, N)

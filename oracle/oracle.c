@@ -313,11 +313,13 @@ int oracle_adjoint(const ogrid *g, const double *vel, const double *rec_data,
  * Forward levels are kept every ckpt_every steps (as the pair u^{kC}, u^{kC-1})
  * and each segment is recomputed exactly before its adjoint steps; ckpt_every
  * <= 0 keeps every level. Outputs (each may be NULL): grad_m = dL/dm,
- * grad_vel = -2 v^-3 grad_m, grad_wavelet [nt][nsrc] = P lambda^n.            */
-int oracle_gradient(const ogrid *g, const double *vel, const double *wavelet,
-                    const double *src_xyz, int nsrc, const double *rec_xyz, int nrec,
-                    const double *rec_grad, int64_t ckpt_every, double *grad_m,
-                    double *grad_vel, double *grad_wavelet) {
+ * grad_vel = -2 v^-3 grad_m, grad_wavelet [nt][nsrc] = P lambda^n, and the
+ * zero-lag cross-correlation image = sum_{n=1..nt} u^n lambda^n of the forward
+ * field with the adjoint field driven by rec_grad (lambda^{nt} = 0).          */
+int oracle_gradient_image(const ogrid *g, const double *vel, const double *wavelet,
+                          const double *src_xyz, int nsrc, const double *rec_xyz, int nrec,
+                          const double *rec_grad, int64_t ckpt_every, double *grad_m,
+                          double *grad_vel, double *grad_wavelet, double *image) {
   if (check_grid(g)) return -1;
   int64_t N = g->nx * g->ny * g->nz, nt = g->nt;
   int64_t C = (ckpt_every <= 0 || ckpt_every > nt) ? (nt > 0 ? nt : 1) : ckpt_every;
@@ -328,6 +330,7 @@ int oracle_gradient(const ogrid *g, const double *vel, const double *wavelet,
   double *gam = malloc(sizeof(double) * N);
   double *lap = malloc(sizeof(double) * N), *q = malloc(sizeof(double) * N);
   double *gm = calloc(N, sizeof(double));
+  double *img = calloc(N, sizeof(double));
   coefficients(g, vel, C2, b);
   oracle_sponge_3d(g, gam);
   /* checkpoints: ck[s] = (u^{sC}, u^{sC-1}) */
@@ -360,6 +363,9 @@ int oracle_gradient(const ogrid *g, const double *vel, const double *wavelet,
                lev + (n - n0 + 2) * N);
     }
     for (int64_t n = n1 - 1; n >= n0; --n) {
+      /* image term j = n+1: u^{n+1} lambda^{n+1} (l1 still holds lambda^{n+1}) */
+      const double *ujp = lev + (n - n0 + 2) * N;
+      for (int64_t p = 0; p < N; ++p) img[p] += ujp[p] * l1[p];
       memset(q, 0, sizeof(double) * N);
       if (nrec) points_spread(&pr, rec_grad + n * nrec, q);
       leapfrog(g, C2, b, l1, l2, q, lap, l2);
@@ -374,12 +380,21 @@ int oracle_gradient(const ogrid *g, const double *vel, const double *wavelet,
     }
   }
   if (grad_m) memcpy(grad_m, gm, sizeof(double) * N);
+  if (image) memcpy(image, img, sizeof(double) * N);
   if (grad_vel)
     for (int64_t p = 0; p < N; ++p) grad_vel[p] = -2.0 * gm[p] / (vel[p] * vel[p] * vel[p]);
-  free(C2); free(b); free(gam); free(lap); free(q); free(gm); free(ck); free(lev);
+  free(C2); free(b); free(gam); free(lap); free(q); free(gm); free(img); free(ck); free(lev);
   free(l1); free(l2);
   points_free(&ps); points_free(&pr);
   return 0;
+}
+
+int oracle_gradient(const ogrid *g, const double *vel, const double *wavelet,
+                    const double *src_xyz, int nsrc, const double *rec_xyz, int nrec,
+                    const double *rec_grad, int64_t ckpt_every, double *grad_m,
+                    double *grad_vel, double *grad_wavelet) {
+  return oracle_gradient_image(g, vel, wavelet, src_xyz, nsrc, rec_xyz, nrec, rec_grad,
+                               ckpt_every, grad_m, grad_vel, grad_wavelet, NULL);
 }
 
 /* Number of threads OpenMP would use (for reporting).                        */

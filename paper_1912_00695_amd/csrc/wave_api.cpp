@@ -582,10 +582,19 @@ int wave_adjoint(const wave_grid* g, const float* vel, const float* rec_data,
   return WAVE_OK;
 }
 
-int wave_gradient(const wave_grid* g, const float* vel, const float* wavelet,
-                  const double* src_xyz_h, int nsrc, const double* rec_xyz_h, int nrec,
-                  const float* rec_grad, const float* ckpt, int ckpt_every, float* grad_vel,
-                  float* grad_wavelet, void* workspace, size_t ws_bytes, void* hip_stream) {
+}  // extern "C"
+
+namespace wave {
+// Backward pass shared by the gradient and the image: forward levels from the
+// checkpoints (or an internal forward pass), segment recompute, adjoint steps
+// driven by rec_adj that accumulate either the velocity gradient (image false)
+// or the zero-lag cross-correlation of the two fields (image true) into graw.
+int backward_accumulate(const wave_grid* g, const float* vel, const float* wavelet,
+                        const double* src_xyz_h, int nsrc, const double* rec_xyz_h, int nrec,
+                        const float* rec_grad, const float* ckpt, int ckpt_every, bool image,
+                        float* out, float* grad_wavelet, void* workspace, size_t ws_bytes,
+                        void* hip_stream) {
+  float* grad_vel = out;
   int st = validate(g);
   if (st) return st;
   if (vel == nullptr || grad_vel == nullptr || nsrc < 0 || nrec < 0) return WAVE_EINVAL;
@@ -653,6 +662,7 @@ int wave_gradient(const wave_grid* g, const float* vel, const float* wavelet,
       a.out = lam[n & 1];
       a.ufwd = seg + (int64_t)(n - n0 + 2) * F;
       a.grad = graw;
+      a.acc_image = image ? 1 : 0;
       set_inj(a, C, 1, nrec, nrec > 0 ? rec_grad + (int64_t)n * nrec : nullptr);
       set_samp(a, C, 0, nsrc,
                (grad_wavelet != nullptr && nsrc > 0 && n + 1 <= nt - 1)
@@ -666,9 +676,34 @@ int wave_gradient(const wave_grid* g, const float* vel, const float* wavelet,
     HIP_TRY(launch_sample(lam[0], ST_F32, LevelMeta{}, 0, C.at<int>(P.samp_idx),
                           C.at<float>(P.samp_w), nsrc, grad_wavelet, C.s));
   }
-  // dL/dm = -graw / dt^2  ->  dL/dv = -2 v^-3 dL/dm = (2 / dt^2) graw / v^3
-  HIP_TRY(launch_grad_finalize(graw, vel, grad_vel, C.G, 2.0 / (g->dt * g->dt), C.s));
+  if (image) {
+    HIP_TRY(launch_unpack(graw, out, C.G, C.s));
+  } else {
+    // dL/dm = -graw / dt^2  ->  dL/dv = -2 v^-3 dL/dm = (2 / dt^2) graw / v^3
+    HIP_TRY(launch_grad_finalize(graw, vel, grad_vel, C.G, 2.0 / (g->dt * g->dt), C.s));
+  }
   return WAVE_OK;
 }
+}  // namespace wave
+
+extern "C" {
+
+int wave_gradient(const wave_grid* g, const float* vel, const float* wavelet,
+                  const double* src_xyz_h, int nsrc, const double* rec_xyz_h, int nrec,
+                  const float* rec_grad, const float* ckpt, int ckpt_every, float* grad_vel,
+                  float* grad_wavelet, void* workspace, size_t ws_bytes, void* hip_stream) {
+  return backward_accumulate(g, vel, wavelet, src_xyz_h, nsrc, rec_xyz_h, nrec, rec_grad, ckpt,
+                             ckpt_every, false, grad_vel, grad_wavelet, workspace, ws_bytes,
+                             hip_stream);
+}
+
+int wave_rtm(const wave_grid* g, const float* vel, const float* wavelet,
+             const double* src_xyz_h, int nsrc, const double* rec_xyz_h, int nrec,
+             const float* rec_data, const float* ckpt, int ckpt_every, float* image,
+             void* workspace, size_t ws_bytes, void* hip_stream) {
+  return backward_accumulate(g, vel, wavelet, src_xyz_h, nsrc, rec_xyz_h, nrec, rec_data, ckpt,
+                             ckpt_every, true, image, nullptr, workspace, ws_bytes, hip_stream);
+}
+
 
 }  // extern "C"

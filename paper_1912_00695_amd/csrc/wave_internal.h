@@ -86,9 +86,11 @@ struct StepArgs {
   const float* samp_w;         // [nsamp][8]
   int nsamp;
   float* samp_out;             // row of nsamp outputs, or null for none
-  // fused gradient accumulation: grad += ufwd * c2 * (L_h cur + injection)
+  // fused accumulation (gradient kernels): grad += ufwd * c2 * (L_h cur + injection),
+  // or with acc_image set grad += ufwd * cur (zero-lag cross-correlation image)
   const float* ufwd;
   float* grad;
+  int acc_image;
   // reduced-precision storage: level index n of `cur`, and the bookkeeping
   int level;
   LevelMeta meta;

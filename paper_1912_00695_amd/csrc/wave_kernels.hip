@@ -10,7 +10,8 @@
 //   * sampling of `cur` at receiver points (extra workgroups after the stencil
 //     workgroups; `cur` is read-only during the step, so sampling the previous
 //     step's result here needs no extra launch),
-//   * optionally the gradient accumulation grad += ufwd * c2 (L_h cur + inj).
+//   * optionally the gradient accumulation grad += ufwd * c2 (L_h cur + inj), or the
+//     imaging condition grad += ufwd * cur.
 //
 // Memory plan per step (FP32): read cur, prev, c2 and write out once each from
 // HBM -- 16 bytes per point; halo re-reads of cur are served by L2. With 16-bit
@@ -372,8 +373,9 @@ __device__ __forceinline__ void step_tile(const StepArgs& a, const int t, const 
         float* gp = a.grad + at;
         float4 gv = ld4(gp);
         const float4 uf = ld4(a.ufwd + at);
-        gv.x = fmaf(uf.x, src.x, gv.x); gv.y = fmaf(uf.y, src.y, gv.y);
-        gv.z = fmaf(uf.z, src.z, gv.z); gv.w = fmaf(uf.w, src.w, gv.w);
+        const float4 f = a.acc_image ? q[R] : src;
+        gv.x = fmaf(uf.x, f.x, gv.x); gv.y = fmaf(uf.y, f.y, gv.y);
+        gv.z = fmaf(uf.z, f.z, gv.z); gv.w = fmaf(uf.w, f.w, gv.w);
         st4(gp, gv);
       }
     }

@@ -20,7 +20,7 @@ MODE_FORWARD, MODE_ADJOINT, MODE_GRADIENT = 0, 1, 2
 
 # Entry points declared in include/wave.h.
 SYMBOLS = ["wave_cfl_dt_max", "wave_workspace_bytes", "wave_checkpoint_bytes", "wave_forward",
-           "wave_adjoint", "wave_gradient", "wave_status_string", "wave_version"]
+           "wave_adjoint", "wave_gradient", "wave_rtm", "wave_status_string", "wave_version"]
 
 
 class WaveError(RuntimeError):
@@ -68,6 +68,8 @@ def lib():
         L.wave_adjoint.restype = i
         L.wave_gradient.argtypes = [gp, fp, fp, dp, i, dp, i, fp, fp, i, fp, fp, vp, sz, vp]
         L.wave_gradient.restype = i
+        L.wave_rtm.argtypes = [gp, fp, fp, dp, i, dp, i, fp, fp, i, fp, vp, sz, vp]
+        L.wave_rtm.restype = i
         L.wave_status_string.argtypes = [i]
         L.wave_status_string.restype = ctypes.c_char_p
         L.wave_version.argtypes = []
@@ -224,3 +226,29 @@ def gradient(grid, vel, wavelet, src_xyz, rec_xyz, rec_grad, ckpt=None, ckpt_eve
     if st != OK:
         raise WaveError(st, "wave_gradient")
     return {"grad_vel": gv, "grad_wavelet": gw}
+
+
+def rtm(grid, vel, wavelet, src_xyz, rec_xyz, rec_data, ckpt=None, ckpt_every=0, workspace=None,
+        stream=None):
+    """Zero-lag cross-correlation image sum_n u^n lambda^n of the forward field with the
+    backward field driven by rec_data. Returns the image [nz][ny][nx]."""
+    vel = _dev_f32(vel, grid.shape, "vel")
+    dev = vel.device
+    src = _host_xyz(src_xyz)
+    rec = _host_xyz(rec_xyz)
+    ns, nr, nt = src.shape[0], rec.shape[0], grid.nt
+    wav = _dev_f32(wavelet, (nt, ns), "wavelet") if ns else None
+    rd = _dev_f32(rec_data, (nt, nr), "rec_data") if nr else None
+    if ckpt is not None:
+        ckpt = ckpt.contiguous()
+    img = torch.empty(grid.shape, dtype=torch.float32, device=dev)
+    nbytes = workspace_bytes(grid, ns, nr, MODE_GRADIENT, ckpt_every)
+    if nbytes == 0:
+        raise WaveError(EINVAL, "wave_workspace_bytes")
+    ws = _workspace(nbytes, dev, workspace)
+    st = lib().wave_rtm(ctypes.byref(grid), _ptr(vel), _ptr(wav), _hptr(src), ns, _hptr(rec), nr,
+                        _ptr(rd), _ptr(ckpt), int(ckpt_every), _ptr(img), _ptr(ws), ws.numel(),
+                        _stream(dev, stream))
+    if st != OK:
+        raise WaveError(st, "wave_rtm")
+    return img

@@ -161,3 +161,23 @@ def test_gradient_finite_differences_c3():
         print("direction", seed, "fd", fd, "adjoint", an, "rel", abs(fd - an) / abs(fd),
               flush=True)
         assert abs(fd - an) <= 1e-2 * abs(fd)
+
+
+@pytest.mark.parametrize("so,ckpt", [(4, 0), (8, 9)])
+def test_rtm_image_matches_oracle(so, ckpt):
+    from paper_1912_00695_amd import wave
+    case = ragged_case(so, nt=40, seed=17)
+    rng = np.random.default_rng(so + 100)
+    d = rng.standard_normal((case.nt, len(case.rec))).astype(np.float32)
+    want = oracle.rtm_image(case.ogrid(), case.vel, case.wavelet, case.src, case.rec, d,
+                            ckpt_every=ckpt)
+    g = case.wgrid()
+    ck = None
+    if ckpt:
+        ck = wave.forward(g, _t(case.vel), _t(case.wavelet), case.src, case.rec,
+                          ckpt_every=ckpt)["ckpt"]
+    img = wave.rtm(g, _t(case.vel), _t(case.wavelet), case.src, case.rec, _t(d), ckpt=ck,
+                   ckpt_every=ckpt).cpu().numpy()
+    e = rel_l2(img, want)
+    print("rtm SO", so, "ckpt", ckpt, "rel-L2", e, flush=True)
+    assert np.abs(want).max() > 0 and e <= 1e-4
