@@ -77,7 +77,9 @@ extern "C" {
 #define WAVE_MODE_GRADIENT 2
 
 typedef struct {
-  int32_t nx, ny, nz;  /* grid points per axis, sponge included                       */
+  int32_t nx, ny, nz;  /* grid points per axis, sponge included; with the row pitch
+                          px = nx rounded up to a multiple of 32, px*ny*nz < 2^31 and
+                          px*ny*4 < 2^31 (else WAVE_EINVAL)                          */
   double hx, hy, hz;   /* spacing [m]                                                 */
   int32_t so;          /* space order, even, 2..24 (stencil radius so/2)              */
   double dt;           /* time step [s], at most wave_cfl_dt_max(so, vmax, hx, hy, hz) */

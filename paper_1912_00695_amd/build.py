@@ -18,24 +18,28 @@ COMMON = ["-O3", "-std=c++17", "-fPIC", "-Wall", "-ffp-contract=fast",
           "--offload-arch=gfx950", "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops"]
 
 
-def build(verbose: bool = False) -> str:
+def build(verbose: bool = False, lib: str = LIB, defines=()) -> str:
+    """Compile and link; defines are extra -D options (tuning switches such as
+    WAVE_ZUNROLL_MASK), lib the output path."""
     objs = []
+    odir = os.path.dirname(os.path.abspath(lib))
     for src in SOURCES:
-        obj = os.path.join(CSRC, src + ".o")
+        obj = os.path.join(odir, src + ".o")
         lang = [] if src.endswith(".hip") else ["-x", "hip"]
-        cmd = [HIPCC] + COMMON + lang + ["-c", os.path.join(CSRC, src), "-o", obj]
+        cmd = ([HIPCC] + COMMON + ["-D" + d for d in defines] + lang
+               + ["-c", os.path.join(CSRC, src), "-o", obj])
         if verbose:
             print(" ".join(cmd), flush=True)
         subprocess.run(cmd, check=True)
         objs.append(obj)
-    cmd = [HIPCC, "--offload-arch=gfx950", "-shared", "-fPIC"] + objs + ["-o", LIB + ".tmp"]
+    cmd = [HIPCC, "--offload-arch=gfx950", "-shared", "-fPIC"] + objs + ["-o", lib + ".tmp"]
     if verbose:
         print(" ".join(cmd), flush=True)
     subprocess.run(cmd, check=True)
-    os.replace(LIB + ".tmp", LIB)
+    os.replace(lib + ".tmp", lib)
     for o in objs:
         os.remove(o)
-    return LIB
+    return lib
 
 
 if __name__ == "__main__":

@@ -52,6 +52,8 @@ bool grid_ok(const wave_grid* g) {
   if (st == WAVE_STORE_F32 && (g->storage & WAVE_STORE_DIFF)) return false;
   const int64_t pitch = (g->nx + 31) / 32 * 32;
   if (pitch * g->ny * (int64_t)g->nz >= ((int64_t)1 << 31)) return false;
+  // one FP32 plane must stay below 2 GiB (the kernels' buffer loads use 32-bit offsets)
+  if (pitch * g->ny * (int64_t)sizeof(float) >= ((int64_t)1 << 31)) return false;
   return true;
 }
 
@@ -75,18 +77,18 @@ int env_int(const char* name, int dflt) {
 // measured on MI355X at 256^3 SO8, 32-plane chunks beat 16 (1024 workgroups) by
 // ~10 % and 48/64 lose to load imbalance and low occupancy. WAVE_ZCHUNK overrides
 // the chunk length (tuning sweeps).
-Tiling make_tiling(const Geom& G) {
+Tiling make_tiling(const Geom& G, int zchunk) {
   Tiling T;
   T.ntile_x = (G.nx + TX - 1) / TX;
   T.ntile_y = (G.ny + TY - 1) / TY;
   const int bxy = T.ntile_x * T.ntile_y;
-  int zc = env_int("WAVE_ZCHUNK", 0);
+  int zc = zchunk > 0 ? zchunk : env_int("WAVE_ZCHUNK", 0);
   if (zc <= 0) {
     const int want = std::max(1, (512 + bxy - 1) / bxy);
     zc = (G.nz + want - 1) / want;
     zc = std::min(std::max(zc, 8), 32);
   }
-  zc = std::max(1, std::min(zc, G.nz));
+  zc = std::max(1, std::min({zc, G.nz, MAXZCHUNK}));
   T.zchunk = zc;
   T.nchunk = (G.nz + zc - 1) / zc;
   T.nblocks = bxy * T.nchunk;
@@ -113,7 +115,9 @@ Layout make_layout(const wave_grid* g, int nsrc, int nrec, int mode, int ckpt_ev
   L.u[0] = take(ubytes);
   L.u[1] = take(ubytes);
   L.d = store_diff(g) ? take(ubytes) : 0;
-  L.meta = store_kind(g) != WAVE_STORE_F32 ? take((size_t)5 * (g->nt + 3) * sizeof(unsigned)) : 0;
+  L.meta = store_kind(g) != WAVE_STORE_F32
+               ? take((size_t)(2 * kMaxSlots + 3) * (g->nt + 3) * sizeof(unsigned))
+               : 0;
   L.tables_beg = off;
   L.bx = take((size_t)G.pitch * sizeof(float));
   L.by = take((size_t)G.ny * sizeof(float));
@@ -268,10 +272,10 @@ void sponge_1d(int n, int lo, int hi, double h, double vmax, double dt, float* b
 void delete_blob(void* p) { delete static_cast<Blob*>(p); }
 
 int init_ctx(Ctx& C, const wave_grid* g, int nsrc, int nrec, int mode, int ckpt_every, void* ws,
-             size_t ws_bytes, void* stream) {
+             size_t ws_bytes, void* stream, int zchunk) {
   C.g = g;
   C.G = make_geom(g);
-  C.T = make_tiling(C.G);
+  C.T = make_tiling(C.G, zchunk);
   C.L = make_layout(g, nsrc, nrec, mode, ckpt_every);
   if (ws == nullptr || (reinterpret_cast<uintptr_t>(ws) % kAlign) != 0) return WAVE_EINVAL;
   if (ws_bytes < C.L.total) return WAVE_ENOMEM;
@@ -344,10 +348,10 @@ LevelMeta level_meta(const Ctx& C) {
   const int64_t L = C.g->nt + 3;
   unsigned* base = C.at<unsigned>(C.L.meta);
   m.mu = base;
-  m.md = base + L;
-  m.injb = reinterpret_cast<float*>(base + 2 * L);
-  m.eu = reinterpret_cast<int*>(base + 3 * L);
-  m.ed = reinterpret_cast<int*>(base + 4 * L);
+  m.md = base + kMaxSlots * L;
+  m.injb = reinterpret_cast<float*>(base + 2 * kMaxSlots * L);
+  m.eu = reinterpret_cast<int*>(base + (2 * kMaxSlots + 1) * L);
+  m.ed = reinterpret_cast<int*>(base + (2 * kMaxSlots + 2) * L);
   return m;
 }
 
@@ -410,7 +414,7 @@ int forward_reduced(Ctx& C, const float* wavelet, int nsrc, int nrec, float* rec
   const LevelMeta meta = level_meta(C);
   void* U[2] = {C.ws + C.L.u[0], C.ws + C.L.u[1]};
   void* D = diff ? C.ws + C.L.d : nullptr;
-  HIP_TRY(launch_zero_words(meta.mu, (int64_t)5 * (g->nt + 3), C.s));
+  HIP_TRY(launch_zero_words(meta.mu, (int64_t)(2 * kMaxSlots + 3) * (g->nt + 3), C.s));
   const float c2max = (float)(g->vmax * g->vmax * g->dt * g->dt);
   if (nsrc > 0) HIP_TRY(launch_inj_bound(wavelet, g->nt, nsrc, c2max, meta.injb, C.s));
   HIP_TRY(launch_encode_initial(u0, um1, U[0], diff ? D : U[1], stk, diff, meta, 0, C.G, C.s));

@@ -47,6 +47,7 @@ namespace {
 constexpr int kReplaySteps = 16;    // launches per space order in one captured graph (even)
 constexpr double kSyncWork = 2e-3;  // GPU seconds of work enqueued between host syncs
 constexpr double kUpdateRate = 250e9;  // grid-point updates per second, for that estimate
+constexpr int kEngineZChunk = 32;      // z-chunk length of resident shots
 
 double now_s() {
   using namespace std::chrono;
@@ -387,7 +388,11 @@ class Engine {
   int start_upload(Shot* s) {
     char* base = static_cast<char*>(pool_) + s->off;
     const wave_grid* g = &s->g;
-    int st = init_ctx(s->C, g, s->nsrc, s->nrec, WAVE_MODE_FORWARD, 0, base, s->bytes, s_up_);
+    // Resident shots share each launch, so parallelism comes from the batch: the
+    // engine tiles every shot with 32-plane z-chunks (fewer priming re-reads than
+    // the single-solve policy gives small grids; the values do not depend on it).
+    int st = init_ctx(s->C, g, s->nsrc, s->nrec, WAVE_MODE_FORWARD, 0, base, s->bytes, s_up_,
+                      kEngineZChunk);
     if (st) return st;
     s->C.g = &s->g;
     s->off_wav = s->C.L.total;

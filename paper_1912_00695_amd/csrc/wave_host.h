@@ -64,11 +64,12 @@ bool grid_ok(const wave_grid* g);
 int validate(const wave_grid* g);  // grid_ok + stability limit
 bool points_ok(const wave_grid* g, const double* xyz, int np);
 Geom make_geom(const wave_grid* g);
-Tiling make_tiling(const Geom& G);
+// zchunk > 0 fixes the z-chunk length; 0 applies the single-solve policy
+Tiling make_tiling(const Geom& G, int zchunk = 0);
 Layout make_layout(const wave_grid* g, int nsrc, int nrec, int mode, int ckpt_every);
 // geometry, tiling, layout and weights of a call on workspace ws (no device work)
 int init_ctx(Ctx& C, const wave_grid* g, int nsrc, int nrec, int mode, int ckpt_every, void* ws,
-             size_t ws_bytes, void* stream);
+             size_t ws_bytes, void* stream, int zchunk = 0);
 Blob* build_blob(const Ctx& C, const double* src, int nsrc, const double* rec, int nrec);
 StepArgs base_args(const Ctx& C);
 void set_inj(StepArgs& a, const Ctx& C, int set, int np, const float* row);

@@ -16,6 +16,7 @@ constexpr int VX = 4;
 constexpr int NTX = TX / VX;     // threads along x
 constexpr int NTHREADS = NTX * TY;
 constexpr int MAXR = 12;         // SO <= 24
+constexpr int MAXZCHUNK = 64;    // planes per z-chunk at most
 constexpr int SAMPLE_THREADS = 256;
 
 // Pitched field geometry: rows padded to a multiple of 32 floats (128 bytes);
@@ -43,11 +44,15 @@ enum StoreKind { ST_F32 = 0, ST_F16 = 1, ST_BF16 = 2 };
 // Reduced-precision levels are stored as value * 2^e (e an integer chosen per level
 // so that the level's bound maps below 2^kScaleTarget). Per-level bookkeeping in
 // device memory, L = nt + 3 entries each, level m at index m + 1:
-//   mu[m+1], md[m+1]  bits of max|u^m| and max|u^m - u^{m-1}| (atomicMax of the
-//                     non-negative float bits written while encoding level m)
+//   mu[(m+1)*kMaxSlots + s], md[...]  bits of max|u^m| and max|u^m - u^{m-1}|
+//                     (atomicMax of the non-negative float bits written while
+//                     encoding level m); workgroup b updates slot b % kMaxSlots, so
+//                     the atomics of one launch spread over kMaxSlots addresses, and
+//                     the level's maximum is the maximum over its slots
 //   injb[n]           bound on the injected increment of step n
 //   eu[m+1], ed[m+1]  scale exponents of level m's u and difference arrays
 constexpr int kScaleTarget = 12;
+constexpr int kMaxSlots = 32;
 struct LevelMeta {
   unsigned* mu;
   unsigned* md;

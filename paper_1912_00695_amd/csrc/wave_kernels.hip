@@ -47,10 +47,6 @@ __device__ __forceinline__ int remap_tile(int b, int nb) {
   return base + k;
 }
 
-
-// Wavefield element access per storage kind: 4 consecutive values (16-byte or
-// 8-byte aligned) or 1 value, widened to / narrowed from FP32 (round to nearest
-// even).
 // Element access per storage kind: 4 consecutive values (16- or 8-byte aligned)
 // or 1 value, widened to / narrowed from FP32 (round to nearest even). NT selects
 // non-temporal loads/stores (streamed once per step, not kept in the caches).
@@ -65,13 +61,47 @@ template <bool NT, class V>
 __device__ __forceinline__ void vstore(V* p, const V& v) {
   if constexpr (NT) __builtin_nontemporal_store(v, p); else *p = v;
 }
+// Range-checked buffer loads (the CDNA buffer resource): a lane whose byte offset
+// is kOOB, or every lane of a resource with zero records, reads zeros without a
+// memory access, so predicated loads need no branch. Each resource is based at
+// one plane of one array (offsets stay below 2^31; the host bounds plane bytes).
+constexpr unsigned kOOB = 0x80000000u;
+constexpr int kBufWord3 = 0x00020000;  // resource word 3 for gfx9-family raw buffers
+typedef int i4v __attribute__((ext_vector_type(4)));
+typedef int i2v __attribute__((ext_vector_type(2)));
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t plane_rsrc(const void* base, int64_t byte_off,
+                                                             int bytes) {
+  return __builtin_amdgcn_make_buffer_rsrc(
+      const_cast<char*>(static_cast<const char*>(base)) + byte_off, (short)0, bytes, kBufWord3);
+}
+template <bool NT>
+__device__ __forceinline__ i4v bload16(__amdgpu_buffer_rsrc_t r, unsigned off) {
+  return __builtin_amdgcn_raw_buffer_load_b128(r, off, 0, NT ? 2 : 0);  // aux bit 1: nt
+}
+template <bool NT>
+__device__ __forceinline__ i2v bload8(__amdgpu_buffer_rsrc_t r, unsigned off) {
+  return __builtin_amdgcn_raw_buffer_load_b64(r, off, 0, NT ? 2 : 0);
+}
+
 template <int ST> struct Store;
+// Each kind also exposes its raw 4-value vector (Raw), a raw load (ldr) and the
+// widening to FP32 (widen), so that loads issued ahead of their use are not
+// followed at once by a conversion that would wait for them.
 template <> struct Store<ST_F32> {
+  using Raw = f4v;
+  __device__ static Raw zero() { return Raw{0.f, 0.f, 0.f, 0.f}; }
   template <bool NT = false>
-  __device__ static float4 ld(const void* b, int64_t i) {
-    const f4v v = vload<NT>(reinterpret_cast<const f4v*>(static_cast<const float*>(b) + i));
-    return make_float4(v.x, v.y, v.z, v.w);
+  __device__ static Raw ldr(const void* b, int64_t i) {
+    return vload<NT>(reinterpret_cast<const f4v*>(static_cast<const float*>(b) + i));
   }
+  static constexpr int kBytes = 4;
+  template <bool NT = false>
+  __device__ static Raw ldb(__amdgpu_buffer_rsrc_t r, unsigned off) {
+    return __builtin_bit_cast(Raw, bload16<NT>(r, off));
+  }
+  __device__ static float4 widen(const Raw& v) { return make_float4(v.x, v.y, v.z, v.w); }
+  template <bool NT = false>
+  __device__ static float4 ld(const void* b, int64_t i) { return widen(ldr<NT>(b, i)); }
   __device__ static float ld1(const void* b, int64_t i) { return static_cast<const float*>(b)[i]; }
   template <bool NT = false>
   __device__ static void st(void* b, int64_t i, const float4& v) {
@@ -81,11 +111,22 @@ template <> struct Store<ST_F32> {
   }
 };
 template <> struct Store<ST_F16> {
+  using Raw = h4v;
+  __device__ static Raw zero() { return Raw{0, 0, 0, 0}; }
   template <bool NT = false>
-  __device__ static float4 ld(const void* b, int64_t i) {
-    const h4v h = vload<NT>(reinterpret_cast<const h4v*>(static_cast<const _Float16*>(b) + i));
+  __device__ static Raw ldr(const void* b, int64_t i) {
+    return vload<NT>(reinterpret_cast<const h4v*>(static_cast<const _Float16*>(b) + i));
+  }
+  static constexpr int kBytes = 2;
+  template <bool NT = false>
+  __device__ static Raw ldb(__amdgpu_buffer_rsrc_t r, unsigned off) {
+    return __builtin_bit_cast(Raw, bload8<NT>(r, off));
+  }
+  __device__ static float4 widen(const Raw& h) {
     return make_float4((float)h.x, (float)h.y, (float)h.z, (float)h.w);
   }
+  template <bool NT = false>
+  __device__ static float4 ld(const void* b, int64_t i) { return widen(ldr<NT>(b, i)); }
   __device__ static float ld1(const void* b, int64_t i) {
     return (float)static_cast<const _Float16*>(b)[i];
   }
@@ -101,13 +142,23 @@ __device__ __forceinline__ unsigned bf16_rne(float f) {
   return (u + 0x7fffu + ((u >> 16) & 1u)) >> 16;
 }
 template <> struct Store<ST_BF16> {
+  using Raw = u2v;
+  __device__ static Raw zero() { return Raw{0u, 0u}; }
   template <bool NT = false>
-  __device__ static float4 ld(const void* b, int64_t i) {
-    const u2v r =
-        vload<NT>(reinterpret_cast<const u2v*>(static_cast<const unsigned short*>(b) + i));
+  __device__ static Raw ldr(const void* b, int64_t i) {
+    return vload<NT>(reinterpret_cast<const u2v*>(static_cast<const unsigned short*>(b) + i));
+  }
+  static constexpr int kBytes = 2;
+  template <bool NT = false>
+  __device__ static Raw ldb(__amdgpu_buffer_rsrc_t r, unsigned off) {
+    return __builtin_bit_cast(Raw, bload8<NT>(r, off));
+  }
+  __device__ static float4 widen(const Raw& r) {
     return make_float4(__uint_as_float(r.x << 16), __uint_as_float(r.x & 0xffff0000u),
                        __uint_as_float(r.y << 16), __uint_as_float(r.y & 0xffff0000u));
   }
+  template <bool NT = false>
+  __device__ static float4 ld(const void* b, int64_t i) { return widen(ldr<NT>(b, i)); }
   __device__ static float ld1(const void* b, int64_t i) {
     return __uint_as_float((unsigned)static_cast<const unsigned short*>(b)[i] << 16);
   }
@@ -154,6 +205,20 @@ __device__ __forceinline__ float sample_point(const void* f, float dec, const in
 }
 }  // namespace
 
+// z-sweep variants per radius, chosen from a sweep of the forms over the space
+// orders on gfx950: bit R of WAVE_ZUNROLL_MASK runs two planes per loop iteration
+// (constant LDS buffer index in each); bit R of WAVE_PF2_MASK issues the loads of
+// plane z+2 while plane z is computed (two planes of loads in flight; implies the
+// two-plane iteration).
+#ifndef WAVE_ZUNROLL_MASK
+#define WAVE_ZUNROLL_MASK 0x1114  // radii 2, 4, 8, 12
+#endif
+#ifndef WAVE_PF2_MASK
+#define WAVE_PF2_MASK 0x0
+#endif
+constexpr bool zunroll2(int r) { return ((WAVE_ZUNROLL_MASK) >> r) & 1; }
+constexpr bool prefetch2(int r) { return ((WAVE_PF2_MASK) >> r) & 1; }
+
 // One tile of one step: the z-sweep of a TX x TY column block over one z-chunk.
 // Shared by the single-shot kernel and the batched serving kernel, so a shot's
 // values do not depend on what else is in the launch.
@@ -169,6 +234,8 @@ __device__ __forceinline__ void step_tile(const StepArgs& a, const int t, const 
   constexpr int NHP = (NH + NTHREADS - 1) / NTHREADS;
   __shared__ float4 lds[2][LROWS * LROW4];
   __shared__ float4 inj[TY * NTX];
+  __shared__ float bzs[MAXZCHUNK];  // z sponge factors of the chunk (read from LDS in the
+                                    // sweep, so no vector load there waits on the prefetch)
 
   const int tx_t = t % a.ntile_x;
   const int rest = t / a.ntile_x;
@@ -185,14 +252,6 @@ __device__ __forceinline__ void step_tile(const StepArgs& a, const int t, const 
   const bool colok = (x0 < nx) && (y < ny);
   const int col = y * a.g.pitch + x0;
   const float4 zero4 = make_float4(0.f, 0.f, 0.f, 0.f);
-  auto ldc = [&](int64_t i) {
-    const float4 v = Store<ST>::template ld<false>(a.cur, i);
-    if constexpr (ST == ST_F32) return v; else return mul4(v, dec_c);
-  };
-  auto ldp = [&](int64_t i) {
-    const float4 v = Store<ST>::template ld<NT>(a.prev, i);
-    if constexpr (ST == ST_F32) return v; else return mul4(v, dec_p);
-  };
   float mx_u = 0.f, mx_d = 0.f;  // running maxima of the written level (reduced precision)
 
   // Halo items of this thread (fixed for the whole z sweep).
@@ -224,29 +283,65 @@ __device__ __forceinline__ void step_tile(const StepArgs& a, const int t, const 
     hoff[k] = hok[k] ? gy * a.g.pitch + gx : 0;
   }
 
+  // Plane resources and per-lane byte offsets of the streamed loads; a plane
+  // outside [0, nz) or past the chunk gets a resource with no records.
+  constexpr int ES = Store<ST>::kBytes;
+  const int pbytes = (int)(plane * ES), pbytes4 = (int)(plane * 4);
+  auto rs_at = [&](const void* f, const int zz, const int es, const int bytes, const bool valid) {
+    const int zc = min(max(zz, 0), nz - 1);
+    return plane_rsrc(f, (int64_t)zc * plane * es, valid ? bytes : 0);
+  };
+  auto rs_cur = [&](const int zz, const bool valid) { return rs_at(a.cur, zz, ES, pbytes, valid); };
+  auto rs_prev = [&](const int zz, const bool valid) { return rs_at(a.prev, zz, ES, pbytes, valid); };
+  auto rs_c2 = [&](const int zz, const bool valid) { return rs_at(a.c2, zz, 4, pbytes4, valid); };
+  const unsigned vo_col = colok ? (unsigned)col * ES : kOOB;
+  const unsigned vo_c2 = colok ? (unsigned)col * 4 : kOOB;
+  unsigned vo_h[NHP];
+#pragma unroll
+  for (int k = 0; k < NHP; ++k) vo_h[k] = hok[k] ? (unsigned)hoff[k] * ES : kOOB;
+
   // Sponge factors: b = bx[x] + by[y] + bz[z].
   const float4 bxv = colok ? ld4(a.bx + x0) : zero4;
   const float byv = y < ny ? a.by[y] : 0.f;
 
-  // Register queue of planes z-R .. z+R for this thread's four points.
+  // Loads are kept raw until every load of a batch has been issued, then widened
+  // (and decoded) in one go, so that no conversion waits for a single load.
+  using Raw = typename Store<ST>::Raw;
+  auto wcur = [&](const Raw& r) {
+    const float4 v = Store<ST>::widen(r);
+    if constexpr (ST == ST_F32) return v; else return mul4(v, dec_c);
+  };
+  auto wprev = [&](const Raw& r) {
+    const float4 v = Store<ST>::widen(r);
+    if constexpr (ST == ST_F32) return v; else return mul4(v, dec_p);
+  };
+
+  // Register queue of planes z-R .. z+R for this thread's four points; prev and
+  // c2 at the current plane stay raw until the update uses them.
   float4 q[2 * R + 1];
-#pragma unroll
-  for (int s = 0; s <= 2 * R; ++s) {
-    const int z = z0 - R + s;
-    q[s] = (colok && z >= 0 && z < nz) ? ldc(z * plane + col) : zero4;
-  }
+  Raw up;
+  f4v cc;
   {
-    float4 hv[NHP];
+    Raw qr[2 * R + 1], hr[NHP];
 #pragma unroll
-    for (int k = 0; k < NHP; ++k) hv[k] = hok[k] ? ldc(z0 * plane + hoff[k]) : zero4;
+    for (int s = 0; s <= 2 * R; ++s) {
+      const int z = z0 - R + s;
+      qr[s] = Store<ST>::template ldb<false>(rs_cur(z, z >= 0 && z < nz), vo_col);
+    }
+    const auto rh = rs_cur(z0, true);
+#pragma unroll
+    for (int k = 0; k < NHP; ++k) hr[k] = Store<ST>::template ldb<false>(rh, vo_h[k]);
+    up = Store<ST>::template ldb<NT>(rs_prev(z0, true), vo_col);
+    cc = Store<ST_F32>::template ldb<NT>(rs_c2(z0, true), vo_c2);
+#pragma unroll
+    for (int s = 0; s <= 2 * R; ++s) q[s] = wcur(qr[s]);
     lds[0][(ty + R) * LROW4 + XH4 + tx] = q[R];
 #pragma unroll
     for (int k = 0; k < NHP; ++k)
-      if (hlds[k] >= 0) lds[0][hlds[k]] = hv[k];
+      if (hlds[k] >= 0) lds[0][hlds[k]] = wcur(hr[k]);
   }
   inj[tid] = zero4;
-  float4 up = colok ? ldp(z0 * plane + col) : zero4;
-  float4 cc = colok ? Store<ST_F32>::template ld<NT>(a.c2, z0 * plane + col) : zero4;
+  if (tid < z1 - z0) bzs[tid] = a.bz[z0 + tid];
   __syncthreads();
 
   int e = 0, e_end = 0;
@@ -255,23 +350,30 @@ __device__ __forceinline__ void step_tile(const StepArgs& a, const int t, const 
     e_end = a.tile_beg[t + 1];
   }
 
-  for (int z = z0; z < z1; ++z) {
-    const int buf = (z - z0) & 1;
-    const bool more = z + 1 < z1;
-    // Prefetch for plane z+1.
-    float4 nq = zero4, nup = zero4, ncc = zero4;
-    float4 nhv[NHP];
-    {
-      const int zq = z + R + 1;
-      if (colok && more && zq < nz) nq = ldc(zq * plane + col);
+  // Loads that plane zn needs before its own step, kept raw until used: the
+  // queue head (plane zn+R), the xy-halo of plane zn, and prev and c2 at plane zn.
+  struct Ahead {
+    Raw q, up;
+    f4v cc;
+    Raw h[NHP];
+  };
+  auto fetch = [&](const int zn, Ahead& f) {
+    const bool ok = zn < z1;
+    f.q = Store<ST>::template ldb<false>(rs_cur(zn + R, ok && zn + R < nz), vo_col);
+    const auto rh = rs_cur(zn, ok);
 #pragma unroll
-      for (int k = 0; k < NHP; ++k)
-        nhv[k] = (hok[k] && more) ? ldc((z + 1) * plane + hoff[k]) : zero4;
-      if (colok && more) {
-        nup = ldp((z + 1) * plane + col);
-        ncc = Store<ST_F32>::template ld<NT>(a.c2, (z + 1) * plane + col);
-      }
-    }
+    for (int k = 0; k < NHP; ++k) f.h[k] = Store<ST>::template ldb<false>(rh, vo_h[k]);
+    f.up = Store<ST>::template ldb<NT>(rs_prev(zn, ok), vo_col);
+    f.cc = Store<ST_F32>::template ldb<NT>(rs_c2(zn, ok), vo_c2);
+  };
+  constexpr bool PF2 = prefetch2(R);
+
+  // One plane of the z-sweep; buf is the LDS buffer that holds plane z, n1 the
+  // loads for plane z+1 (issued here, or one plane earlier with PF2, which then
+  // issues plane z+2's into n2).
+  auto plane_step = [&](const int z, const int buf, Ahead& n1, Ahead& n2) {
+    const bool more = z + 1 < z1;
+    if constexpr (PF2) fetch(z + 2, n2); else fetch(z + 1, n1);
 
     // Laplacian of plane z.
     const float4* L = lds[buf];
@@ -336,14 +438,16 @@ __device__ __forceinline__ void step_tile(const StepArgs& a, const int t, const 
     // smooth fields, so the only rounding at the magnitude of u is the final add.
     // In the difference form prev already holds d = u^n - u^{n-1} and the new
     // difference is stored beside u^{n+1}.
-    const float bzv = a.bz[z];
+    const float bzv = bzs[z - z0];
+    const float4 upv = wprev(up);
+    const float4 ccv = Store<ST_F32>::widen(cc);
     float4 o, dn, src;
 #pragma unroll
     for (int p = 0; p < 4; ++p) {
       const float b = (comp(bxv, p) + byv) + bzv;
       const float u = comp(q[R], p);
-      const float d = DIFF ? comp(up, p) : u - comp(up, p);
-      const float c = comp(cc, p);
+      const float d = DIFF ? comp(upv, p) : u - comp(upv, p);
+      const float c = comp(ccv, p);
       if constexpr (GRAD) set_comp(src, p, c * lap[p]);
       const float num = fmaf(c, lap[p], fmaf(-b, d, d));
       const float inv = __builtin_amdgcn_rcpf(1.f + b);
@@ -385,24 +489,61 @@ __device__ __forceinline__ void step_tile(const StepArgs& a, const int t, const 
       lds[buf ^ 1][crow] = q[R + 1];
 #pragma unroll
       for (int k = 0; k < NHP; ++k)
-        if (hlds[k] >= 0) lds[buf ^ 1][hlds[k]] = nhv[k];
+        if (hlds[k] >= 0) lds[buf ^ 1][hlds[k]] = wcur(n1.h[k]);
     }
     __syncthreads();
 #pragma unroll
     for (int s = 0; s < 2 * R; ++s) q[s] = q[s + 1];
-    q[2 * R] = nq;
-    up = nup;
-    cc = ncc;
+    q[2 * R] = wcur(n1.q);
+    up = n1.up;
+    cc = n1.cc;
+  };
+  // Two planes per iteration give each call a constant LDS buffer index and swap
+  // the roles of the two load sets without copies (the barriers inside keep the
+  // compiler from unrolling the loop by itself).
+  Ahead fa, fb;
+  if constexpr (PF2) fetch(z0 + 1, fa);
+  int z = z0;
+  if constexpr (PF2 || zunroll2(R)) {
+    for (; z + 1 < z1; z += 2) {
+      plane_step(z, 0, fa, fb);
+      plane_step(z + 1, 1, fb, fa);
+    }
+    if (z < z1) plane_step(z, 0, fa, fb);
+  } else {
+    for (; z < z1; ++z) plane_step(z, (z - z0) & 1, fa, fb);
   }
   if constexpr (ST != ST_F32) {
-    // maxima of the level just written, for the next step's scale choice
+    // Maxima of the level just written, for the next step's scale choice: reduced
+    // over the workgroup, then one atomic per workgroup into its slot.
+    __shared__ float wm[2][NTHREADS / 64];
     mx_u = wave_max(mx_u);
     if (DIFF) mx_d = wave_max(mx_d);
-    if ((threadIdx.x & 63) == 0) {
-      atomicMax(a.meta.mu + a.level + 2, __float_as_uint(mx_u));
-      if (DIFF) atomicMax(a.meta.md + a.level + 2, __float_as_uint(mx_d));
+    if ((tid & 63) == 0) {
+      wm[0][tid >> 6] = mx_u;
+      wm[1][tid >> 6] = mx_d;
+    }
+    __syncthreads();
+    if (tid == 0) {
+      float mu = wm[0][0], md = wm[1][0];
+#pragma unroll
+      for (int w = 1; w < NTHREADS / 64; ++w) {
+        mu = fmaxf(mu, wm[0][w]);
+        md = fmaxf(md, wm[1][w]);
+      }
+      const int slot = (a.level + 2) * kMaxSlots + (int)(blockIdx.x % kMaxSlots);
+      atomicMax(a.meta.mu + slot, __float_as_uint(mu));
+      if (DIFF) atomicMax(a.meta.md + slot, __float_as_uint(md));
     }
   }
+}
+
+// Maximum recorded for bookkeeping entry i (a level index + 1) over its slots.
+__device__ __forceinline__ float level_max(const unsigned* arr, int i) {
+  unsigned m = 0;
+#pragma unroll
+  for (int s = 0; s < kMaxSlots; ++s) m = max(m, arr[i * kMaxSlots + s]);
+  return __uint_as_float(m);
 }
 
 template <int R, bool GRAD, int ST, bool DIFF, bool NT>
@@ -414,16 +555,16 @@ __global__ void __launch_bounds__(NTHREADS) step_kernel(const StepArgs a) {
     const int n = a.level;
     dec_c = ldexpf(1.f, -a.meta.eu[n + 1]);
     dec_p = ldexpf(1.f, DIFF ? -a.meta.ed[n + 1] : -a.meta.eu[n]);
-    const float mun = __uint_as_float(a.meta.mu[n + 1]);
+    const float mun = level_max(a.meta.mu, n + 1);
     const float injb = a.meta.injb[n];
     int eu, ed = 0;
     if constexpr (DIFF) {
       // |d^{n+1}| <= |d^n| + c2 |L u^n| + inj, c2 |L| <= 4 under the CFL limit
-      const float bd = __uint_as_float(a.meta.md[n + 1]) + 4.f * mun + injb;
+      const float bd = level_max(a.meta.md, n + 1) + 4.f * mun + injb;
       ed = scale_exp(bd);
       eu = scale_exp(mun + bd);
     } else {
-      eu = scale_exp(8.f * fmaxf(mun, __uint_as_float(a.meta.mu[n])) + injb);
+      eu = scale_exp(8.f * fmaxf(mun, level_max(a.meta.mu, n)) + injb);
     }
     enc_u = ldexpf(1.f, eu);
     enc_d = ldexpf(1.f, ed);
@@ -598,11 +739,11 @@ __global__ void initial_max_kernel(const float* a, const float* b, bool diff, un
 // Scale exponents of the initial levels (one thread).
 __global__ void initial_scales_kernel(LevelMeta meta, int m, bool diff) {
   if (threadIdx.x != 0 || blockIdx.x != 0) return;
-  meta.eu[m + 1] = scale_exp(__uint_as_float(meta.mu[m + 1]));
+  meta.eu[m + 1] = scale_exp(level_max(meta.mu, m + 1));
   if (diff)
-    meta.ed[m + 1] = scale_exp(__uint_as_float(meta.md[m + 1]));
+    meta.ed[m + 1] = scale_exp(level_max(meta.md, m + 1));
   else
-    meta.eu[m] = scale_exp(__uint_as_float(meta.mu[m]));
+    meta.eu[m] = scale_exp(level_max(meta.mu, m));
 }
 
 // Encode initial levels into pitched stores (padding columns zero).
@@ -790,9 +931,10 @@ hipError_t launch_inj_bound(const float* trace, int nt, int ntr, float c2max, fl
 hipError_t launch_encode_initial(const float* a, const float* b, void* ua, void* ub, int st,
                                  bool diff, LevelMeta meta, int m, Geom g, hipStream_t s) {
   const int64_t n = (int64_t)g.nx * g.ny * g.nz;
-  unsigned* slot_b = diff ? meta.md + m + 1 : meta.mu + m;
+  // slot 0 of the entries of levels m and m-1
+  unsigned* slot_b = diff ? meta.md + (m + 1) * kMaxSlots : meta.mu + m * kMaxSlots;
   hipLaunchKernelGGL(initial_max_kernel, dim3(elementwise_blocks(n)), dim3(256), 0, s, a, b, diff,
-                     meta.mu + m + 1, slot_b, n);
+                     meta.mu + (m + 1) * kMaxSlots, slot_b, n);
   hipLaunchKernelGGL(initial_scales_kernel, dim3(1), dim3(64), 0, s, meta, m, diff);
   const dim3 grid(elementwise_blocks(g.nfield / 4)), block(256);
   if (st == ST_F16)

@@ -6,7 +6,8 @@ error of each format (printed) and check what must hold -- the difference form
 (u, u - u_prev) beats storing two levels, FP16 beats BF16, FP16 in the difference
 form meets rel-L2 <= 1e-2 on the traces (its final-field error, measured at about
 1.2e-2 on the 160^3 case, is bounded at 2e-2), and the per-level power-of-two scales
-make the result independent of the wavefield's magnitude.
+make the result independent of the wavefield's magnitude (exactly for FP16, to
+rounding noise for BF16).
 """
 import numpy as np
 import pytest
@@ -79,11 +80,26 @@ def test_reduced_storage_full_size_vs_fp32():
 @pytest.mark.parametrize("fmt", ["f16", "bf16", "f16_diff", "bf16_diff"])
 def test_scale_invariance(fmt):
     """Wavelets scaled by 2^-30 and 2^+30 (far outside FP16's range without scaling,
-    inside FP32's so the arithmetic itself is unaffected) give the same result scaled
-    by the same power of two."""
+    inside FP32's) against the unscaled run. FP16 storage zeroes the far tails of
+    the wavefield, so the scaled runs equal the unscaled one times the same power of
+    two (rel-L2 <= 1e-6). BF16 keeps FP32's exponent range: the tails reach FP32
+    subnormals at different places in the scaled runs, one rounding differs, and
+    from there the two BF16 trajectories carry independent rounding noise; so for
+    BF16 the check is that a scaled run is as accurate as the unscaled one, both
+    measured against the FP32 run (within a factor 1.5)."""
     case = c4_case(n=(96, 80, 72), nt=300, nbl=12)
     r1, u1 = _run(case, FORMATS[fmt])
+    if fmt.startswith("bf16"):
+        r32, u32 = _run(case, 0)
+        e1u, e1r = rel_l2(u1, u32), rel_l2(r1, r32)
+        print(fmt, "unscaled vs FP32: field %.3e traces %.3e" % (e1u, e1r), flush=True)
     for e in (-30, 30):
         r2, u2 = _run(case, FORMATS[fmt], scale=2.0 ** e)
-        print(fmt, "scale 2^%d: rel %.3e" % (e, rel_l2(u2 * 2.0 ** -e, u1)), flush=True)
-        assert rel_l2(u2 * 2.0 ** -e, u1) <= 1e-6 and rel_l2(r2 * 2.0 ** -e, r1) <= 1e-6
+        u2, r2 = u2 * 2.0 ** -e, r2 * 2.0 ** -e
+        print(fmt, "scale 2^%d: rel %.3e" % (e, rel_l2(u2, u1)), flush=True)
+        if fmt.startswith("f16"):
+            assert rel_l2(u2, u1) <= 1e-6 and rel_l2(r2, r1) <= 1e-6
+        else:
+            e2u, e2r = rel_l2(u2, u32), rel_l2(r2, r32)
+            print(fmt, "scale 2^%d vs FP32: field %.3e traces %.3e" % (e, e2u, e2r), flush=True)
+            assert e2u <= 1.5 * e1u + 1e-6 and e2r <= 1.5 * e1r + 1e-6
