@@ -205,11 +205,15 @@ def cpu_baseline(P, target_s=20.0):
     same 256^3 SO8 workload."""
     import numpy as np
     import oracle
+    # a 2-step run first (thread start-up and first touch of the arrays), then a
+    # 6-step run to estimate the time per step, then the timed sample
     og = oracle.Grid(P["n"], P["h"], P["so"], P["dt"], 2, nbl=P["nbl"], vmax=P["vmax"])
-    t0 = time.perf_counter()
     oracle.forward(og, P["vel"], P["wav"][:2], P["src"], P["rec"])
-    per_step = (time.perf_counter() - t0) / 2
-    nsteps = int(max(2, min(200, target_s / max(per_step, 1e-6))))
+    og = og.replace(nt=6)
+    t0 = time.perf_counter()
+    oracle.forward(og, P["vel"], P["wav"][:6], P["src"], P["rec"])
+    per_step = (time.perf_counter() - t0) / 6
+    nsteps = int(max(2, min(P["nt"], target_s / max(per_step, 1e-6))))
     og = og.replace(nt=nsteps)
     t0 = time.perf_counter()
     oracle.forward(og, P["vel"], P["wav"][:nsteps], P["src"], P["rec"])

@@ -84,9 +84,18 @@ Tiling make_tiling(const Geom& G, int zchunk) {
   const int bxy = T.ntile_x * T.ntile_y;
   int zc = zchunk > 0 ? zchunk : env_int("WAVE_ZCHUNK", 0);
   if (zc <= 0) {
+    // about 512 workgroups (two per CU) with chunks of 8..32 planes
     const int want = std::max(1, (512 + bxy - 1) / bxy);
     zc = (G.nz + want - 1) / want;
     zc = std::min(std::max(zc, 8), 32);
+    // Grids that need more than 1024 workgroups at 32-plane chunks run in several
+    // rounds of resident workgroups: balanced chunks of about 20 planes keep the
+    // planes swept at once within the caches (measured on MI355X: +7-10 % at 384^3
+    // and 512^3 over 32-plane chunks; 256^3 stays at 32).
+    if ((int64_t)bxy * ((G.nz + 31) / 32) > 1024) {
+      const int nch = (G.nz + 19) / 20;
+      zc = (G.nz + nch - 1) / nch;
+    }
   }
   zc = std::max(1, std::min({zc, G.nz, MAXZCHUNK}));
   T.zchunk = zc;

@@ -211,7 +211,7 @@ __device__ __forceinline__ float sample_point(const void* f, float dec, const in
 // plane z+2 while plane z is computed (two planes of loads in flight; implies the
 // two-plane iteration).
 #ifndef WAVE_ZUNROLL_MASK
-#define WAVE_ZUNROLL_MASK 0x1114  // radii 2, 4, 8, 12
+#define WAVE_ZUNROLL_MASK 0x1FFE  // every radius 1..12
 #endif
 #ifndef WAVE_PF2_MASK
 #define WAVE_PF2_MASK 0x0
