@@ -27,6 +27,7 @@ HBM_PEAK_GBS = 8000.0          # MI355X HBM3E, published
 ALG_BYTES_PER_PT = 16          # read u^n, u^{n-1}, v^2 dt^2; write u^{n+1} (FP32)
 METRIC = "Gpt-updates/s and % HBM roofline at 256^3 SO4-16; p50/p99 shot latency"
 KERNEL_SOURCES = ["paper_1912_00695_amd/csrc/wave_kernels.hip",
+                  "paper_1912_00695_amd/csrc/wave_device.h",
                   "paper_1912_00695_amd/csrc/wave_internal.h"]
 COUNTERS_FILE = os.path.join(ROOT, "profiles", "step_kernel_256cube_so8_counters.md")
 
@@ -149,6 +150,27 @@ def reduced_precision_leg(dev):
         res[name] = item
         log("lowp %s: %s" % (name, item))
         del ws, out, u, r, recb
+    return res
+
+
+def two_step_leg(dev):
+    """Temporal blocking: the forward solve with two fused leapfrog steps per launch
+    against one step per launch, same workloads as the sweep and the 512^3 control
+    (FP32; 20 algorithmic bytes per point per two-step launch)."""
+    res = {}
+    for n, so, nt in ((256, 4, 500), (256, 8, 500), (512, 4, 100), (512, 8, 100)):
+        item = {}
+        for name, flag in (("two_step", "1"), ("one_step", "0")):
+            os.environ["WAVE_FUSED"] = flag
+            S = Solver(c2_problem(so, nt=nt, n=(n, n, n)), dev)
+            e, _ = time_solves(S, 2, 1)
+            item[name + "_gpts"] = round(n ** 3 * nt * 2 / e / 1e9, 2)
+            del S
+        os.environ.pop("WAVE_FUSED", None)
+        item["speedup"] = round(item["two_step_gpts"] / item["one_step_gpts"], 3)
+        res["%d^3_so%d" % (n, so)] = item
+        log("two-step %d^3 SO%d: %s" % (n, so, item))
+    res["default"] = "two-step kernel used by default for SO <= 4 on grids beyond the cache"
     return res
 
 
@@ -317,6 +339,7 @@ def main():
         del S
     if not args.no_sweep:
         out["lowp_512_so8"] = reduced_precision_leg(dev)
+        out["two_step_kernel"] = two_step_leg(dev)
     if not args.no_serving:
         out["serving"] = serving_leg(dev, args.serving_requests)
     if not args.no_cpu:

@@ -11,7 +11,7 @@ import sys
 HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libwave.so")
-SOURCES = ["wave_kernels.hip", "wave_api.cpp", "wave_engine.cpp"]
+SOURCES = ["wave_kernels.hip", "wave_fused.hip", "wave_api.cpp", "wave_engine.cpp"]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 COMMON = ["-O3", "-std=c++17", "-fPIC", "-Wall", "-ffp-contract=fast",

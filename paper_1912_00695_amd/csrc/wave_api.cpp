@@ -142,7 +142,22 @@ Layout make_layout(const wave_grid* g, int nsrc, int nrec, int mode, int ckpt_ev
     L.pts[s].samp_idx = take(n8 * sizeof(int));
     L.pts[s].samp_w = take(n8 * sizeof(float));
   }
+  L.fused = mode == WAVE_MODE_FORWARD && store_kind(g) == WAVE_STORE_F32 && g->so / 2 <= 4;
+  if (L.fused) {
+    // each corner of a source lies in the extended region of at most 2 tiles per
+    // axis (x extension 4 < TX, y extension r <= 4 < TY, z extension r <= 4 <= half
+    // the shortest chunk)
+    const size_t n64 = (size_t)64 * std::max(nsrc, 0);
+    L.epts.tile_beg = take((size_t)(max_tiles(G) + 1) * sizeof(int));
+    L.epts.ent = take(n64 * sizeof(InjEntry));
+    L.epts.csr_idx = take(n64 * sizeof(int));
+    L.epts.csr_w = take(n64 * sizeof(float));
+  }
   L.tables_end = off;
+  if (L.fused) {
+    L.ux[0] = take(fbytes);
+    L.ux[1] = take(fbytes);
+  }
   if (mode == WAVE_MODE_GRADIENT) {
     const int C = ckpt_every > 0 ? ckpt_every : kDefaultCkpt;
     L.ckpt_every = C;
@@ -263,6 +278,94 @@ void build_point_tables(const wave_grid* g, const Geom& G, const Tiling& T, cons
   }
 }
 
+// The two-step kernel needs chunks of at least 2r planes (a source corner then
+// lies in the extended region of at most two chunks, which sizes its tables).
+bool fused_tiling_ok(const Ctx& C) { return C.L.fused && C.T.zchunk >= C.g->so; }
+
+// Whether a forward solve takes the two-step kernel. Measured on MI355X it wins
+// only where one step's arrays exceed the 256 MiB Infinity Cache and the radius is
+// at most 2 (512^3 SO4: +8 %); where the cache holds the working set (256^3) or at
+// radius 3-4 (160 registers per lane, one 512-thread workgroup per CU) the
+// one-step kernel is faster. WAVE_FUSED=1 forces it (radius <= 4), 0 disables it.
+bool use_fused(const Ctx& C) {
+  const int force = env_int("WAVE_FUSED", -1);
+  if (force >= 0) return force != 0;
+  return C.g->so / 2 <= 2 && C.nt;
+}
+
+// Source tables of the two-step kernel: for every tile, the grid points of its
+// extended region (x in [xt - 4, xt + TX + 4), y in [yt - r, yt + TY + r), z in
+// [z0 - r, z1 + r)), with local index row * (TX + 8) + column in that region.
+// A point near a tile edge appears in the tables of every tile whose region
+// holds it; each copy carries its own (point, weight) terms in the same order.
+void build_ext_tables(const wave_grid* g, const Geom& G, const Tiling& T, int r, const double* xyz,
+                      int np, const PointTables& P, Blob& B) {
+  constexpr int XE = 4;
+  int* tile_beg = B.at<int>(P.tile_beg);
+  const int ntiles = T.nblocks;
+  std::fill(tile_beg, tile_beg + ntiles + 1, 0);
+  struct Key {
+    int tile, z, local;
+    bool operator<(const Key& o) const {
+      return tile != o.tile ? tile < o.tile : z != o.z ? z < o.z : local < o.local;
+    }
+  };
+  std::map<Key, std::vector<std::pair<int, float>>> uniq;
+  for (int p = 0; p < np; ++p) {
+    int ijk[24], c = 0;
+    double w[8];
+    corners(g, xyz + 3 * p, ijk, w, &c);
+    for (int k = 0; k < c; ++k) {
+      const int i = ijk[3 * k], j = ijk[3 * k + 1], z = ijk[3 * k + 2];
+      for (int tx = std::max(0, i / TX - 1); tx <= std::min(T.ntile_x - 1, i / TX + 1); ++tx) {
+        const int xt = tx * TX;
+        if (i < xt - XE || i >= xt + TX + XE) continue;
+        for (int ty = std::max(0, j / TY - 1); ty <= std::min(T.ntile_y - 1, j / TY + 1); ++ty) {
+          const int yt = ty * TY;
+          if (j < yt - r || j >= yt + TY + r) continue;
+          for (int zc = std::max(0, z / T.zchunk - 1);
+               zc <= std::min(T.nchunk - 1, z / T.zchunk + 1); ++zc) {
+            const int z0 = zc * T.zchunk, z1 = std::min(z0 + T.zchunk, G.nz);
+            if (z < z0 - r || z >= z1 + r) continue;
+            const int tile = (zc * T.ntile_y + ty) * T.ntile_x + tx;
+            const int local = (j - (yt - r)) * (TX + 2 * XE) + (i - (xt - XE));
+            uniq[Key{tile, z, local}].push_back({p, (float)w[k]});
+          }
+        }
+      }
+    }
+  }
+  InjEntry* ent = B.at<InjEntry>(P.ent);
+  int* cidx = B.at<int>(P.csr_idx);
+  float* cw = B.at<float>(P.csr_w);
+  int e = 0, c = 0;
+  for (auto& kv : uniq) {
+    InjEntry en{};
+    en.z = kv.first.z;
+    en.local = kv.first.local;
+    en.csr_beg = c;
+    for (auto& pw : kv.second) {
+      cidx[c] = pw.first;
+      cw[c] = pw.second;
+      ++c;
+    }
+    en.csr_end = c;
+    ent[e] = en;
+    tile_beg[kv.first.tile + 1]++;
+    ++e;
+  }
+  for (int t = 0; t < ntiles; ++t) tile_beg[t + 1] += tile_beg[t];
+  for (int t = 0; t < ntiles; ++t) {
+    int b = tile_beg[t], end = tile_beg[t + 1];
+    while (b < end) {
+      int q = b;
+      while (q < end && ent[q].z == ent[b].z) ++q;
+      for (int k = b; k < q; ++k) ent[k].grp_end = q;
+      b = q;
+    }
+  }
+}
+
 void sponge_1d(int n, int lo, int hi, double h, double vmax, double dt, float* b) {
   const double pi = 3.14159265358979323846;
   std::vector<double> gam(n, 0.0);
@@ -328,6 +431,7 @@ Blob* build_blob(const Ctx& C, const double* src, int nsrc, const double* rec, i
   sponge_1d(g->nz, g->nbl[4], g->nbl[5], g->hz, g->vmax, g->dt, B->at<float>(C.L.bz));
   build_point_tables(g, C.G, C.T, src, nsrc, C.L.pts[0], *B);
   build_point_tables(g, C.G, C.T, rec, nrec, C.L.pts[1], *B);
+  if (fused_tiling_ok(C)) build_ext_tables(g, C.G, C.T, g->so / 2, src, nsrc, C.L.epts, *B);
   return B;
 }
 
@@ -455,6 +559,74 @@ int forward_reduced(Ctx& C, const float* wavelet, int nsrc, int nrec, float* rec
   return WAVE_OK;
 }
 
+// FP32 forward solve with two fused steps per launch (radius <= 4). Four level
+// buffers: a pass reads u^n and u^{n-1} (with halos, also from neighbouring
+// workgroups) and writes u^{n+1} and u^{n+2} into the other two. A pass at n >= 2
+// also samples its two input levels: d^{n-1} = R u^n and d^{n-2} = R u^{n-1}. An
+// odd step count ends with one single step.
+int forward_fused(Ctx& C, const float* wavelet, int nsrc, int nrec, float* rec_out,
+                  const float* u0, const float* um1, float* u_final) {
+  const wave_grid* g = C.g;
+  float* X[4] = {C.at<float>(C.L.u[0]), C.at<float>(C.L.u[1]), C.at<float>(C.L.ux[0]),
+                 C.at<float>(C.L.ux[1])};
+  HIP_TRY(launch_pack(u0, X[0], C.G, C.s));
+  HIP_TRY(launch_pack(um1, X[1], C.G, C.s));
+  HIP_TRY(launch_pack(nullptr, X[2], C.G, C.s));  // padding columns are never written
+  HIP_TRY(launch_pack(nullptr, X[3], C.G, C.s));
+  const int r = g->so / 2;
+  const PointTables& PR = C.L.pts[1];
+  Fused2Args f{};
+  f.a = base_args(C);
+  int cur = 0, prv = 1, o1 = 2, o2 = 3;
+  int n = 0;
+  for (; n + 2 <= g->nt; n += 2) {
+    f.a.cur = X[cur];
+    f.a.prev = X[prv];
+    f.a.out = X[o1];
+    f.out2 = X[o2];
+    set_inj(f.a, C, 0, nsrc, nsrc > 0 ? wavelet + (int64_t)(n + 1) * nsrc : nullptr);
+    if (nsrc > 0) {
+      f.etile_beg = C.at<int>(C.L.epts.tile_beg);
+      f.eent = C.at<InjEntry>(C.L.epts.ent);
+      f.ecsr_idx = C.at<int>(C.L.epts.csr_idx);
+      f.ecsr_w = C.at<float>(C.L.epts.csr_w);
+      f.etrace_row = wavelet + (int64_t)n * nsrc;
+    }
+    set_samp(f.a, C, 1, nrec, n >= 2 && nrec > 0 ? rec_out + (int64_t)(n - 1) * nrec : nullptr);
+    f.samp_out2 = n >= 2 && nrec > 0 ? rec_out + (int64_t)(n - 2) * nrec : nullptr;
+    HIP_TRY(launch_fused2(f, r, C.nt, C.s));
+    const int oc = cur, op = prv;
+    cur = o2;
+    prv = o1;
+    o1 = op;
+    o2 = oc;
+  }
+  // Levels now: X[cur] = u^n, X[prv] = u^{n-1}.
+  if (nrec > 0 && n >= 2)  // d^{n-2}, before a single step overwrites u^{n-1}
+    HIP_TRY(launch_sample(X[prv], ST_F32, LevelMeta{}, 0, C.at<int>(PR.samp_idx),
+                          C.at<float>(PR.samp_w), nrec, rec_out + (int64_t)(n - 2) * nrec, C.s));
+  int last = cur;
+  if (n < g->nt) {
+    StepArgs a = base_args(C);
+    a.cur = X[cur];
+    a.prev = X[prv];
+    a.out = X[prv];
+    set_inj(a, C, 0, nsrc, nsrc > 0 ? wavelet + (int64_t)n * nsrc : nullptr);
+    set_samp(a, C, 1, nrec, n >= 1 && nrec > 0 ? rec_out + (int64_t)(n - 1) * nrec : nullptr);
+    HIP_TRY(launch_step(a, r, false, ST_F32, false, C.nt, C.s));
+    last = prv;
+  } else if (nrec > 0 && n >= 1) {  // d^{n-1} = R u^n (even step count)
+    HIP_TRY(launch_sample(X[cur], ST_F32, LevelMeta{}, 0, C.at<int>(PR.samp_idx),
+                          C.at<float>(PR.samp_w), nrec, rec_out + (int64_t)(n - 1) * nrec, C.s));
+  }
+  if (nrec > 0 && n < g->nt)  // d^{nt-1} = R u^{nt} after the final single step
+    HIP_TRY(launch_sample(X[last], ST_F32, LevelMeta{}, 0, C.at<int>(PR.samp_idx),
+                          C.at<float>(PR.samp_w), nrec, rec_out + (int64_t)(g->nt - 1) * nrec,
+                          C.s));
+  if (u_final != nullptr) HIP_TRY(launch_unpack(X[last], u_final, C.G, C.s));
+  return WAVE_OK;
+}
+
 int validate(const wave_grid* g) {
   if (!grid_ok(g)) return WAVE_EINVAL;
   const double dtm = wave_cfl_dt_max(g->so, g->vmax, g->hx, g->hy, g->hz);
@@ -525,6 +697,8 @@ int wave_forward(const wave_grid* g, const float* vel, const float* wavelet,
   if (st) return st;
   if (store_kind(g) != WAVE_STORE_F32)
     return forward_reduced(C, wavelet, nsrc, nrec, rec_out, u0, um1, u_final);
+  if (ckpt == nullptr && fused_tiling_ok(C) && use_fused(C))
+    return forward_fused(C, wavelet, nsrc, nrec, rec_out, u0, um1, u_final);
   float* X[2] = {C.at<float>(C.L.u[0]), C.at<float>(C.L.u[1])};
   HIP_TRY(launch_pack(u0, X[0], C.G, C.s));
   HIP_TRY(launch_pack(um1, X[1], C.G, C.s));

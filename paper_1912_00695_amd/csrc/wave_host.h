@@ -26,6 +26,9 @@ struct PointTables {  // offsets into the workspace
 struct Layout {
   size_t c2, bx, by, bz, u[2], d, meta;
   PointTables pts[2];  // 0: sources, 1: receivers
+  bool fused;          // FP32 forward with radius <= 4: two more levels and the
+  size_t ux[2];        //   extended-tile source tables of the two-step kernel
+  PointTables epts;
   size_t tables_beg, tables_end;
   size_t graw, lam[2], seg, ick;  // gradient mode
   int ckpt_every, nseg;

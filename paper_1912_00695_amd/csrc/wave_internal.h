@@ -101,6 +101,23 @@ struct StepArgs {
   LevelMeta meta;
 };
 
+// Two fused leapfrog steps per pass (FP32 forward, radius <= 4): u^n, u^{n-1} ->
+// u^{n+1}, u^{n+2}. In `a`: cur = u^n, prev = u^{n-1}, out = u^{n+1}; the tile
+// injection tables with trace_row = step n+1's samples (added to u^{n+2});
+// sampling of cur into samp_out. The extended-tile tables inject step n's samples
+// into u^{n+1} over each tile's extended region.
+constexpr int F2_THREADS = 512;
+struct Fused2Args {
+  StepArgs a;
+  float* out2;               // u^{n+2}
+  const int* etile_beg;      // [ntiles + 1] entries over the extended tiles
+  const InjEntry* eent;      // local = row * (TX + 8) + column within the extended tile
+  const int* ecsr_idx;
+  const float* ecsr_w;
+  const float* etrace_row;   // step n's samples, or null
+  float* samp_out2;          // samples of prev (u^{n-1}), or null
+};
+
 // Serving: a resident shot and one entry of a batched launch's tile table.
 struct ShotDesc {
   StepArgs a;              // static per-shot arguments (tables, geometry, weights)
@@ -120,6 +137,8 @@ struct BatchEntry {
 // non-temporal loads/stores of the streamed arrays (prev, c2, out).
 hipError_t launch_step(const StepArgs& a, int r, bool grad, int st, bool diff, bool nt,
                        hipStream_t s);
+// two fused steps (radius r <= 4); nt: non-temporal stores of the two outputs
+hipError_t launch_fused2(const Fused2Args& f, int r, bool nt, hipStream_t s);
 // one batched step of every shot in table (space-order radius r, launch parity)
 hipError_t launch_batched(ShotDesc* shots, const BatchEntry* table, int nentries, int r,
                           int parity, hipStream_t s);

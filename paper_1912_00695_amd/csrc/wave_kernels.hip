@@ -17,193 +17,12 @@
 // HBM -- 16 bytes per point; halo re-reads of cur are served by L2. With 16-bit
 // wavefield storage (FP16 / BF16, FP32 arithmetic) the naive form moves
 // 2+2+4+2 = 10 bytes per point and the difference form (u, u - u_prev) 12.
-#include "wave_internal.h"
+#include <climits>
+
+#include "wave_device.h"
 
 namespace wave {
 
-namespace {
-
-__device__ __forceinline__ float4 ld4(const float* p) {
-  return *reinterpret_cast<const float4*>(p);
-}
-__device__ __forceinline__ void st4(float* p, const float4& v) {
-  *reinterpret_cast<float4*>(p) = v;
-}
-__device__ __forceinline__ float comp(const float4& v, int i) {
-  return i == 0 ? v.x : i == 1 ? v.y : i == 2 ? v.z : v.w;
-}
-__device__ __forceinline__ void set_comp(float4& v, int i, float s) {
-  if (i == 0) v.x = s; else if (i == 1) v.y = s; else if (i == 2) v.z = s; else v.w = s;
-}
-
-
-// Block id -> logical tile id. Workgroups are dealt round-robin to the 8 XCDs;
-// remapping gives each XCD a contiguous run of logical tiles (whole xy-planes
-// of consecutive z-chunks), so tiles that exchange halos share one L2.
-__device__ __forceinline__ int remap_tile(int b, int nb) {
-  const int q = nb >> 3, rem = nb & 7;
-  const int xcd = b & 7, k = b >> 3;
-  const int base = xcd < rem ? xcd * (q + 1) : rem * (q + 1) + (xcd - rem) * q;
-  return base + k;
-}
-
-// Element access per storage kind: 4 consecutive values (16- or 8-byte aligned)
-// or 1 value, widened to / narrowed from FP32 (round to nearest even). NT selects
-// non-temporal loads/stores (streamed once per step, not kept in the caches).
-typedef float f4v __attribute__((ext_vector_type(4)));
-typedef _Float16 h4v __attribute__((ext_vector_type(4)));
-typedef unsigned u2v __attribute__((ext_vector_type(2)));
-template <bool NT, class V>
-__device__ __forceinline__ V vload(const V* p) {
-  if constexpr (NT) return __builtin_nontemporal_load(p); else return *p;
-}
-template <bool NT, class V>
-__device__ __forceinline__ void vstore(V* p, const V& v) {
-  if constexpr (NT) __builtin_nontemporal_store(v, p); else *p = v;
-}
-// Range-checked buffer loads (the CDNA buffer resource): a lane whose byte offset
-// is kOOB, or every lane of a resource with zero records, reads zeros without a
-// memory access, so predicated loads need no branch. Each resource is based at
-// one plane of one array (offsets stay below 2^31; the host bounds plane bytes).
-constexpr unsigned kOOB = 0x80000000u;
-constexpr int kBufWord3 = 0x00020000;  // resource word 3 for gfx9-family raw buffers
-typedef int i4v __attribute__((ext_vector_type(4)));
-typedef int i2v __attribute__((ext_vector_type(2)));
-__device__ __forceinline__ __amdgpu_buffer_rsrc_t plane_rsrc(const void* base, int64_t byte_off,
-                                                             int bytes) {
-  return __builtin_amdgcn_make_buffer_rsrc(
-      const_cast<char*>(static_cast<const char*>(base)) + byte_off, (short)0, bytes, kBufWord3);
-}
-template <bool NT>
-__device__ __forceinline__ i4v bload16(__amdgpu_buffer_rsrc_t r, unsigned off) {
-  return __builtin_amdgcn_raw_buffer_load_b128(r, off, 0, NT ? 2 : 0);  // aux bit 1: nt
-}
-template <bool NT>
-__device__ __forceinline__ i2v bload8(__amdgpu_buffer_rsrc_t r, unsigned off) {
-  return __builtin_amdgcn_raw_buffer_load_b64(r, off, 0, NT ? 2 : 0);
-}
-
-template <int ST> struct Store;
-// Each kind also exposes its raw 4-value vector (Raw), a raw load (ldr) and the
-// widening to FP32 (widen), so that loads issued ahead of their use are not
-// followed at once by a conversion that would wait for them.
-template <> struct Store<ST_F32> {
-  using Raw = f4v;
-  __device__ static Raw zero() { return Raw{0.f, 0.f, 0.f, 0.f}; }
-  template <bool NT = false>
-  __device__ static Raw ldr(const void* b, int64_t i) {
-    return vload<NT>(reinterpret_cast<const f4v*>(static_cast<const float*>(b) + i));
-  }
-  static constexpr int kBytes = 4;
-  template <bool NT = false>
-  __device__ static Raw ldb(__amdgpu_buffer_rsrc_t r, unsigned off) {
-    return __builtin_bit_cast(Raw, bload16<NT>(r, off));
-  }
-  __device__ static float4 widen(const Raw& v) { return make_float4(v.x, v.y, v.z, v.w); }
-  template <bool NT = false>
-  __device__ static float4 ld(const void* b, int64_t i) { return widen(ldr<NT>(b, i)); }
-  __device__ static float ld1(const void* b, int64_t i) { return static_cast<const float*>(b)[i]; }
-  template <bool NT = false>
-  __device__ static void st(void* b, int64_t i, const float4& v) {
-    f4v w;
-    w.x = v.x; w.y = v.y; w.z = v.z; w.w = v.w;
-    vstore<NT>(reinterpret_cast<f4v*>(static_cast<float*>(b) + i), w);
-  }
-};
-template <> struct Store<ST_F16> {
-  using Raw = h4v;
-  __device__ static Raw zero() { return Raw{0, 0, 0, 0}; }
-  template <bool NT = false>
-  __device__ static Raw ldr(const void* b, int64_t i) {
-    return vload<NT>(reinterpret_cast<const h4v*>(static_cast<const _Float16*>(b) + i));
-  }
-  static constexpr int kBytes = 2;
-  template <bool NT = false>
-  __device__ static Raw ldb(__amdgpu_buffer_rsrc_t r, unsigned off) {
-    return __builtin_bit_cast(Raw, bload8<NT>(r, off));
-  }
-  __device__ static float4 widen(const Raw& h) {
-    return make_float4((float)h.x, (float)h.y, (float)h.z, (float)h.w);
-  }
-  template <bool NT = false>
-  __device__ static float4 ld(const void* b, int64_t i) { return widen(ldr<NT>(b, i)); }
-  __device__ static float ld1(const void* b, int64_t i) {
-    return (float)static_cast<const _Float16*>(b)[i];
-  }
-  template <bool NT = false>
-  __device__ static void st(void* b, int64_t i, const float4& v) {
-    h4v h;
-    h.x = (_Float16)v.x; h.y = (_Float16)v.y; h.z = (_Float16)v.z; h.w = (_Float16)v.w;
-    vstore<NT>(reinterpret_cast<h4v*>(static_cast<_Float16*>(b) + i), h);
-  }
-};
-__device__ __forceinline__ unsigned bf16_rne(float f) {
-  const unsigned u = __float_as_uint(f);
-  return (u + 0x7fffu + ((u >> 16) & 1u)) >> 16;
-}
-template <> struct Store<ST_BF16> {
-  using Raw = u2v;
-  __device__ static Raw zero() { return Raw{0u, 0u}; }
-  template <bool NT = false>
-  __device__ static Raw ldr(const void* b, int64_t i) {
-    return vload<NT>(reinterpret_cast<const u2v*>(static_cast<const unsigned short*>(b) + i));
-  }
-  static constexpr int kBytes = 2;
-  template <bool NT = false>
-  __device__ static Raw ldb(__amdgpu_buffer_rsrc_t r, unsigned off) {
-    return __builtin_bit_cast(Raw, bload8<NT>(r, off));
-  }
-  __device__ static float4 widen(const Raw& r) {
-    return make_float4(__uint_as_float(r.x << 16), __uint_as_float(r.x & 0xffff0000u),
-                       __uint_as_float(r.y << 16), __uint_as_float(r.y & 0xffff0000u));
-  }
-  template <bool NT = false>
-  __device__ static float4 ld(const void* b, int64_t i) { return widen(ldr<NT>(b, i)); }
-  __device__ static float ld1(const void* b, int64_t i) {
-    return __uint_as_float((unsigned)static_cast<const unsigned short*>(b)[i] << 16);
-  }
-  template <bool NT = false>
-  __device__ static void st(void* b, int64_t i, const float4& v) {
-    u2v r;
-    r.x = bf16_rne(v.x) | (bf16_rne(v.y) << 16);
-    r.y = bf16_rne(v.z) | (bf16_rne(v.w) << 16);
-    vstore<NT>(reinterpret_cast<u2v*>(static_cast<unsigned short*>(b) + i), r);
-  }
-};
-
-__device__ __forceinline__ float4 mul4(const float4& v, float s) {
-  return make_float4(v.x * s, v.y * s, v.z * s, v.w * s);
-}
-
-// Scale exponent e for a level whose magnitudes are bounded by b: b * 2^e stays
-// below 2^kScaleTarget (16x below the FP16 maximum).
-__device__ __forceinline__ int scale_exp(float b) {
-  int e = -126;
-  if (b > 0.f && b <= 3.0e38f) {
-    int ex;
-    frexpf(b, &ex);  // b < 2^ex
-    e = ex;
-  }
-  return min(max(kScaleTarget - e, -120), 120);
-}
-
-__device__ __forceinline__ float wave_max(float v) {
-#pragma unroll
-  for (int o = 32; o >= 1; o >>= 1) v = fmaxf(v, __shfl_xor(v, o, 64));
-  return v;
-}
-
-// Weighted sum over up to 8 trilinear corners (unused corners carry weight 0
-// and index 0) of a stored level, decoded with factor dec.
-template <int ST>
-__device__ __forceinline__ float sample_point(const void* f, float dec, const int* idx,
-                                              const float* w, int r) {
-  float acc = 0.f;
-#pragma unroll
-  for (int c = 0; c < 8; ++c) acc = fmaf(w[8 * r + c], Store<ST>::ld1(f, idx[8 * r + c]) * dec, acc);
-  return acc;
-}
-}  // namespace
 
 // z-sweep variants per radius, chosen from a sweep of the forms over the space
 // orders on gfx950: bit R of WAVE_ZUNROLL_MASK runs two planes per loop iteration
@@ -294,6 +113,9 @@ __device__ __forceinline__ void step_tile(const StepArgs& a, const int t, const 
   auto rs_cur = [&](const int zz, const bool valid) { return rs_at(a.cur, zz, ES, pbytes, valid); };
   auto rs_prev = [&](const int zz, const bool valid) { return rs_at(a.prev, zz, ES, pbytes, valid); };
   auto rs_c2 = [&](const int zz, const bool valid) { return rs_at(a.c2, zz, 4, pbytes4, valid); };
+  auto rs_f32 = [&](const void* f, const int zz, const bool valid) {
+    return rs_at(f, zz, 4, pbytes4, valid);
+  };
   const unsigned vo_col = colok ? (unsigned)col * ES : kOOB;
   const unsigned vo_c2 = colok ? (unsigned)col * 4 : kOOB;
   unsigned vo_h[NHP];
@@ -321,6 +143,7 @@ __device__ __forceinline__ void step_tile(const StepArgs& a, const int t, const 
   float4 q[2 * R + 1];
   Raw up;
   f4v cc;
+  f4v ufc{}, grc{};  // gradient kernels: forward level and accumulator at the plane
   {
     Raw qr[2 * R + 1], hr[NHP];
 #pragma unroll
@@ -333,6 +156,10 @@ __device__ __forceinline__ void step_tile(const StepArgs& a, const int t, const 
     for (int k = 0; k < NHP; ++k) hr[k] = Store<ST>::template ldb<false>(rh, vo_h[k]);
     up = Store<ST>::template ldb<NT>(rs_prev(z0, true), vo_col);
     cc = Store<ST_F32>::template ldb<NT>(rs_c2(z0, true), vo_c2);
+    if constexpr (GRAD) {
+      ufc = Store<ST_F32>::template ldb<false>(rs_f32(a.ufwd, z0, true), vo_c2);
+      grc = Store<ST_F32>::template ldb<false>(rs_f32(a.grad, z0, true), vo_c2);
+    }
 #pragma unroll
     for (int s = 0; s <= 2 * R; ++s) q[s] = wcur(qr[s]);
     lds[0][(ty + R) * LROW4 + XH4 + tx] = q[R];
@@ -344,17 +171,20 @@ __device__ __forceinline__ void step_tile(const StepArgs& a, const int t, const 
   if (tid < z1 - z0) bzs[tid] = a.bz[z0 + tid];
   __syncthreads();
 
-  int e = 0, e_end = 0;
+  // Injection entries of this tile (sorted by plane); ez is the plane of the next
+  // group, kept in a register so the per-plane test needs no load.
+  int e = 0, e_end = 0, ez = INT_MAX;
   if (a.tile_beg != nullptr) {
     e = a.tile_beg[t];
     e_end = a.tile_beg[t + 1];
+    if (e < e_end) ez = a.ent[e].z;
   }
 
   // Loads that plane zn needs before its own step, kept raw until used: the
   // queue head (plane zn+R), the xy-halo of plane zn, and prev and c2 at plane zn.
   struct Ahead {
     Raw q, up;
-    f4v cc;
+    f4v cc, uf, gr;
     Raw h[NHP];
   };
   auto fetch = [&](const int zn, Ahead& f) {
@@ -365,6 +195,10 @@ __device__ __forceinline__ void step_tile(const StepArgs& a, const int t, const 
     for (int k = 0; k < NHP; ++k) f.h[k] = Store<ST>::template ldb<false>(rh, vo_h[k]);
     f.up = Store<ST>::template ldb<NT>(rs_prev(zn, ok), vo_col);
     f.cc = Store<ST_F32>::template ldb<NT>(rs_c2(zn, ok), vo_c2);
+    if constexpr (GRAD) {
+      f.uf = Store<ST_F32>::template ldb<false>(rs_f32(a.ufwd, zn, ok), vo_c2);
+      f.gr = Store<ST_F32>::template ldb<false>(rs_f32(a.grad, zn, ok), vo_c2);
+    }
   };
   constexpr bool PF2 = prefetch2(R);
 
@@ -416,7 +250,7 @@ __device__ __forceinline__ void step_tile(const StepArgs& a, const int t, const 
     }
 
     // Fused injection at this plane (uniform branch).
-    if (e < e_end && a.ent[e].z == z) {
+    if (z == ez) {
       const int ge = a.ent[e].grp_end;
       for (int i = e + tid; i < ge; i += NTHREADS) {
         const InjEntry en = a.ent[i];
@@ -430,6 +264,7 @@ __device__ __forceinline__ void step_tile(const StepArgs& a, const int t, const 
       lap[0] += iv.x; lap[1] += iv.y; lap[2] += iv.z; lap[3] += iv.w;
       inj[tid] = zero4;
       e = ge;
+      ez = e < e_end ? a.ent[e].z : INT_MAX;
     }
 
     // Damped leapfrog update in increment form:
@@ -474,13 +309,12 @@ __device__ __forceinline__ void step_tile(const StepArgs& a, const int t, const 
         }
       }
       if constexpr (GRAD) {
-        float* gp = a.grad + at;
-        float4 gv = ld4(gp);
-        const float4 uf = ld4(a.ufwd + at);
+        const float4 uf = Store<ST_F32>::widen(ufc);
+        float4 gv = Store<ST_F32>::widen(grc);
         const float4 f = a.acc_image ? q[R] : src;
         gv.x = fmaf(uf.x, f.x, gv.x); gv.y = fmaf(uf.y, f.y, gv.y);
         gv.z = fmaf(uf.z, f.z, gv.z); gv.w = fmaf(uf.w, f.w, gv.w);
-        st4(gp, gv);
+        st4(a.grad + at, gv);
       }
     }
 
@@ -497,6 +331,10 @@ __device__ __forceinline__ void step_tile(const StepArgs& a, const int t, const 
     q[2 * R] = wcur(n1.q);
     up = n1.up;
     cc = n1.cc;
+    if constexpr (GRAD) {
+      ufc = n1.uf;
+      grc = n1.gr;
+    }
   };
   // Two planes per iteration give each call a constant LDS buffer index and swap
   // the roles of the two load sets without copies (the barriers inside keep the

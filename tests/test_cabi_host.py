@@ -109,7 +109,11 @@ def test_reduced_storage_workspace_and_limits():
     f16 = wave.workspace_bytes(_grid(n=(64, 64, 64), storage=wave.STORE_F16), 1, 1)
     f16d = wave.workspace_bytes(_grid(n=(64, 64, 64), storage=wave.STORE_F16 | wave.STORE_DIFF),
                                 1, 1)
-    assert f16 < f32 < f16d + 64 ** 3 * 4 and f16 < f16d
+    # FP32 at radius <= 4 holds c2 and four levels (the two-step kernel's buffers);
+    # 16-bit storage holds c2 and two (naive) or three (difference form) 2-byte arrays
+    assert f16 < f16d < f32 and f32 >= 5 * 64 ** 3 * 4 and f16d < 64 ** 3 * (4 + 3 * 2) * 1.1
+    f32_so16 = wave.workspace_bytes(_grid(n=(64, 64, 64), so=16), 1, 1)
+    assert 3 * 64 ** 3 * 4 <= f32_so16 < 4 * 64 ** 3 * 4
     L = wave.lib()
     for st in (wave.STORE_F16, wave.STORE_BF16 | wave.STORE_DIFF):
         g = _grid(storage=st)

@@ -1,0 +1,130 @@
+"""Two fused leapfrog steps per launch (FP32 forward, SO 2..8) against the FP64 oracle
+and against the one-step-per-launch path of the same library.
+
+wave_forward can take the two-step path for FP32 storage, radius <= 4, no
+checkpoints and z-chunks of at least 2r planes; by default it does so only where it
+is faster (radius <= 2 on grids beyond the Infinity Cache). These tests force it
+with WAVE_FUSED=1 and select the single-step path with WAVE_FUSED=0 (the variable is
+read at every call). Tolerances: rel-L2 <= 1e-5 against the oracle
+on traces and final field (FP32 vs FP64), <= 1e-6 between the two GPU paths (both
+evaluate every point's update with the same expression; the bound allows for the
+compiler contracting differently in the two kernels).
+"""
+import os
+
+import numpy as np
+import pytest
+
+from helpers import Case, ragged_case, rel_l2
+from paper_1912_00695_amd import inputs
+
+pytestmark = pytest.mark.gpu
+
+
+def _run(case, fused=True):
+    import torch
+    from paper_1912_00695_amd import wave
+    dev = torch.device("cuda:0")
+    t = lambda a: None if a is None else torch.from_numpy(
+        np.ascontiguousarray(a, dtype=np.float32)).to(dev)
+    old = os.environ.get("WAVE_FUSED")
+    os.environ["WAVE_FUSED"] = "1" if fused else "0"
+    try:
+        out = wave.forward(case.wgrid(), t(case.vel), t(case.wavelet), case.src, case.rec,
+                           u0=t(case.u0), um1=t(case.um1), want_final=True)
+        torch.cuda.synchronize()
+    finally:
+        if old is None:
+            del os.environ["WAVE_FUSED"]
+        else:
+            os.environ["WAVE_FUSED"] = old
+    rec = out["rec"].cpu().numpy() if out.get("rec") is not None else np.zeros((case.nt, 0))
+    return rec, out["u_final"].cpu().numpy()
+
+
+@pytest.mark.parametrize("so,nt", [(2, 45), (4, 46), (6, 45), (8, 46), (8, 45)])
+def test_fused_matches_oracle(so, nt):
+    case = ragged_case(so, nt=nt, seed=so)
+    print("fused ragged SO", so, "nt", nt, flush=True)
+    rec, uf = _run(case)
+    orec, ouf, _ = case.oracle_forward()
+    er, eu = rel_l2(rec, orec), rel_l2(uf, ouf)
+    print("  traces %.3e  field %.3e" % (er, eu), flush=True)
+    assert er <= 1e-5 and eu <= 1e-5
+
+
+@pytest.mark.parametrize("so", [2, 4, 8])
+def test_fused_equals_single_step_path(so):
+    case = ragged_case(so, nt=40, seed=10 + so)
+    print("fused vs single-step SO", so, flush=True)
+    r1, u1 = _run(case, fused=True)
+    r0, u0 = _run(case, fused=False)
+    print("  traces %.3e  field %.3e  bitwise %s" % (rel_l2(r1, r0), rel_l2(u1, u0),
+                                                     np.array_equal(u1, u0)), flush=True)
+    assert rel_l2(r1, r0) <= 1e-6 and rel_l2(u1, u0) <= 1e-6
+
+
+def test_fused_sources_on_tile_and_chunk_edges():
+    """Sources and receivers on and next to tile edges (x = 63, 64; y = 15, 16) and
+    z-chunk edges (z = 31, 32 with 32-plane chunks), where the extended-region
+    injection tables of neighbouring tiles overlap; SO8, 160 x 48 x 70."""
+    n, h = (160, 48, 70), (10.0, 10.0, 10.0)
+    vel = inputs.smooth_random_range(n, 1500.0, 2500.0, 8.0, seed=31)
+    c = Case(n, h, 8, 36, vel, 2500.0, nbl=(6,) * 6)
+    pts = [(63, 15, 31), (64, 16, 32), (63.5, 15.5, 31.5), (127.2, 31.7, 63.9), (2.0, 46.5, 40.0)]
+    c.src = np.array([[p[0] * h[0], p[1] * h[1], p[2] * h[2]] for p in pts])
+    c.wavelet = np.random.default_rng(32).standard_normal((c.nt, len(pts))).astype(np.float32)
+    c.rec = np.concatenate([c.src, inputs.random_points(n, h, 30, 33)])
+    print("fused edge sources SO8", flush=True)
+    rec, uf = _run(c)
+    orec, ouf, _ = c.oracle_forward()
+    er, eu = rel_l2(rec, orec), rel_l2(uf, ouf)
+    print("  traces %.3e  field %.3e" % (er, eu), flush=True)
+    assert er <= 1e-5 and eu <= 1e-5
+
+
+@pytest.mark.parametrize("nt", [0, 1, 2, 3])
+def test_fused_short_runs(nt):
+    case = ragged_case(4, nt=max(nt, 1), seed=40 + nt)
+    case.nt = nt
+    case.wavelet = case.wavelet[:nt]
+    print("fused short run nt", nt, flush=True)
+    rec, uf = _run(case)
+    orec, ouf, _ = case.oracle_forward()
+    assert rec.shape == orec.shape
+    er = rel_l2(rec, orec) if nt else 0.0
+    eu = rel_l2(uf, ouf)
+    print("  traces %.3e  field %.3e" % (er, eu), flush=True)
+    assert er <= 1e-5 and eu <= 1e-5
+
+
+def test_fused_full_size_512_so4_matches_single_step():
+    """512^3 SO4, two-layer model with 40-cell sponge, 60 steps: the default path
+    (two-step kernel: radius 2, arrays beyond the Infinity Cache) against the
+    one-step path, which the full-size tests check against the oracle."""
+    import torch
+    from paper_1912_00695_amd import wave
+    n, h, nt = (512, 512, 512), (10.0, 10.0, 10.0), 60
+    vel = inputs.two_layer(n, 1500.0, 3000.0, 256)
+    c = Case(n, h, 4, nt, vel, 3000.0, nbl=(40,) * 6)
+    c.src = inputs.point((256, 256, 256), h)
+    c.wavelet = inputs.ricker(10.0, c.dt, nt)[:, None]
+    c.rec = inputs.line_x(n, h, 256, 260)
+    print("512^3 SO4 default (two-step) vs one-step", flush=True)
+    os.environ.pop("WAVE_FUSED", None)
+    dev = torch.device("cuda:0")
+    t = lambda a: torch.from_numpy(np.ascontiguousarray(a, dtype=np.float32)).to(dev)
+    outs = []
+    for flag in (None, "0"):
+        if flag is not None:
+            os.environ["WAVE_FUSED"] = flag
+        try:
+            o = wave.forward(c.wgrid(), t(c.vel), t(c.wavelet), c.src, c.rec, want_final=True)
+            outs.append((o["rec"].cpu().numpy(), o["u_final"].cpu().numpy()))
+            del o
+        finally:
+            os.environ.pop("WAVE_FUSED", None)
+    (r1, u1), (r0, u0) = outs
+    print("  traces %.3e  field %.3e" % (rel_l2(r1, r0), rel_l2(u1, u0)), flush=True)
+    assert np.abs(r0).max() > 0
+    assert rel_l2(r1, r0) <= 1e-6 and rel_l2(u1, u0) <= 1e-6
