@@ -174,6 +174,32 @@ def two_step_leg(dev):
     return res
 
 
+def basic_leg(dev):
+    """Ablation after the paper's basic/aggressive experiment (Tables 2-3): the
+    forward solve at 256^3 (the sweep's workload) with the unfactorised update
+    (every term divided by r0 separately) against the factorised kernel, SO 8-24;
+    throughput and rel-L2 of the basic form's traces against the factorised ones."""
+    import numpy as np
+    res = {}
+    for so in (8, 12, 16, 24):
+        item = {}
+        recs = {}
+        for name, flag in (("basic", "1"), ("factorised", "0")):
+            os.environ["WAVE_BASIC"] = flag
+            S = Solver(c2_problem(so), dev)
+            e, _ = time_solves(S, 2, 1)
+            item[name + "_gpts"] = round(256 ** 3 * 500 * 2 / e / 1e9, 2)
+            recs[name] = S.rec_out.double().cpu().numpy()
+            del S
+        os.environ.pop("WAVE_BASIC", None)
+        item["speedup_factorised_over_basic"] = round(item["factorised_gpts"] / item["basic_gpts"], 3)
+        item["basic_traces_rel_l2_vs_factorised"] = float(
+            np.linalg.norm(recs["basic"] - recs["factorised"]) / np.linalg.norm(recs["factorised"]))
+        res["so%d" % so] = item
+        log("basic vs factorised SO%d: %s" % (so, item))
+    return res
+
+
 def serving_leg(dev, nreq):
     """The serving workload: Poisson arrivals at 20/s (seed 5) of forward shots drawn
     from {96^3, 128^3, 192^3, 256^3, 160x160x320} x SO {4, 8} x nt in [200, 1000],
@@ -340,6 +366,7 @@ def main():
     if not args.no_sweep:
         out["lowp_512_so8"] = reduced_precision_leg(dev)
         out["two_step_kernel"] = two_step_leg(dev)
+        out["basic_vs_factorised_256"] = basic_leg(dev)
     if not args.no_serving:
         out["serving"] = serving_leg(dev, args.serving_requests)
     if not args.no_cpu:

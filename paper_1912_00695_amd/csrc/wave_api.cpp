@@ -488,6 +488,7 @@ StepArgs base_args(const Ctx& C) {
     a.wz[q] = (float)C.wz[q];
   }
   a.wc = (float)C.wc;
+  a.dt = (float)C.g->dt;
   return a;
 }
 
@@ -697,7 +698,11 @@ int wave_forward(const wave_grid* g, const float* vel, const float* wavelet,
   if (st) return st;
   if (store_kind(g) != WAVE_STORE_F32)
     return forward_reduced(C, wavelet, nsrc, nrec, rec_out, u0, um1, u_final);
-  if (ckpt == nullptr && fused_tiling_ok(C) && use_fused(C))
+  // WAVE_BASIC=1: the unfactorised ablation kernel (SO 8, 12, 16, 24; one step per
+  // launch; comparison with the paper's basic/aggressive experiment only)
+  const bool basic = env_int("WAVE_BASIC", 0) != 0;
+  if (basic && g->so != 8 && g->so != 12 && g->so != 16 && g->so != 24) return WAVE_EINVAL;
+  if (!basic && ckpt == nullptr && fused_tiling_ok(C) && use_fused(C))
     return forward_fused(C, wavelet, nsrc, nrec, rec_out, u0, um1, u_final);
   float* X[2] = {C.at<float>(C.L.u[0]), C.at<float>(C.L.u[1])};
   HIP_TRY(launch_pack(u0, X[0], C.G, C.s));
@@ -718,7 +723,10 @@ int wave_forward(const wave_grid* g, const float* vel, const float* wavelet,
     a.out = prev;
     set_inj(a, C, 0, nsrc, nsrc > 0 ? wavelet + (int64_t)n * nsrc : nullptr);
     set_samp(a, C, 1, nrec, n >= 1 && nrec > 0 ? rec_out + (int64_t)(n - 1) * nrec : nullptr);
-    HIP_TRY(launch_step(a, r, false, ST_F32, false, C.nt, C.s));
+    if (basic)
+      HIP_TRY(launch_step_basic(a, r, C.s));
+    else
+      HIP_TRY(launch_step(a, r, false, ST_F32, false, C.nt, C.s));
   }
   if (nrec > 0 && g->nt > 0) {
     const PointTables& P = C.L.pts[1];

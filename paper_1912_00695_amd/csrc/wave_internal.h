@@ -80,6 +80,7 @@ struct StepArgs {
   // taken about the centre)
   float wx[MAXR + 1], wy[MAXR + 1], wz[MAXR + 1];
   float wc;
+  float dt;           // time step (the unfactorised ablation kernel only)
   // fused injection into `out`: per-tile entry lists
   const int* tile_beg;         // [ntiles + 1]
   const InjEntry* ent;
@@ -137,6 +138,9 @@ struct BatchEntry {
 // non-temporal loads/stores of the streamed arrays (prev, c2, out).
 hipError_t launch_step(const StepArgs& a, int r, bool grad, int st, bool diff, bool nt,
                        hipStream_t s);
+// ablation: one FP32 forward step in the unfactorised form of the paper's SO2
+// listing (every term divided by r0 separately), radius r in {4, 6, 8, 12}
+hipError_t launch_step_basic(const StepArgs& a, int r, hipStream_t s);
 // two fused steps (radius r <= 4); nt: non-temporal stores of the two outputs
 hipError_t launch_fused2(const Fused2Args& f, int r, bool nt, hipStream_t s);
 // one batched step of every shot in table (space-order radius r, launch parity)

@@ -41,7 +41,7 @@ constexpr bool prefetch2(int r) { return ((WAVE_PF2_MASK) >> r) & 1; }
 // One tile of one step: the z-sweep of a TX x TY column block over one z-chunk.
 // Shared by the single-shot kernel and the batched serving kernel, so a shot's
 // values do not depend on what else is in the launch.
-template <int R, bool GRAD, int ST, bool DIFF, bool NT>
+template <int R, bool GRAD, int ST, bool DIFF, bool NT, bool BASIC = false>
 __device__ __forceinline__ void step_tile(const StepArgs& a, const int t, const float dec_c,
                                           const float dec_p, const float enc_u,
                                           const float enc_d) {
@@ -225,7 +225,8 @@ __device__ __forceinline__ void step_tile(const StepArgs& a, const int t, const 
     // exactly zero and no spurious zeroth-order term builds up in FP32.
     float lap[4];
 #pragma unroll
-    for (int p = 0; p < 4; ++p) lap[p] = a.wc * comp(q[R], p);
+    for (int p = 0; p < 4; ++p) lap[p] = BASIC ? 0.f : a.wc * comp(q[R], p);
+    if constexpr (!BASIC) {
 #pragma unroll
     for (int s = R; s >= 2; --s) {
       const float4 ym = L[crow - s * LROW4];
@@ -247,6 +248,7 @@ __device__ __forceinline__ void step_tile(const StepArgs& a, const int t, const 
         lap[p] = fmaf(a.wy[1], (comp(ym, p) + comp(yp, p)) - u2, lap[p]);
         lap[p] = fmaf(a.wz[1], (comp(q[R - 1], p) + comp(q[R + 1], p)) - u2, lap[p]);
       }
+    }
     }
 
     // Fused injection at this plane (uniform branch).
@@ -277,6 +279,34 @@ __device__ __forceinline__ void step_tile(const StepArgs& a, const int t, const 
     const float4 upv = wprev(up);
     const float4 ccv = Store<ST_F32>::widen(cc);
     float4 o, dn, src;
+    if constexpr (BASIC) {
+      // The unfactorised update of the paper's SO2 listing (Section 2.1), every
+      // term with its own coefficient and its own division by
+      // r0 = dt m + dt^2 damp / 2, with m = dt^2 / c2 and damp = m gamma per point
+      // (here lap holds only the injected samples). Ablation only.
+      const float dt = a.dt, dt2 = dt * dt, dt3 = dt2 * dt;
+#pragma unroll
+      for (int p = 0; p < 4; ++p) {
+        const float c = comp(ccv, p);
+        const float b = (comp(bxv, p) + byv) + bzv;
+        const float u = comp(q[R], p), um = comp(upv, p);
+        const float m = dt2 / c;
+        const float damp = m * (2.f * b / dt);
+        const float r0 = dt * m + 0.5f * dt2 * damp;
+        float acc = -dt * m * um / r0 + dt3 * lap[p] / r0;
+#pragma unroll
+        for (int s = 1; s <= R; ++s) {
+          const float4 ym = L[crow - s * LROW4];
+          const float4 yp = L[crow + s * LROW4];
+          acc += dt3 * a.wx[s] * xv[XH + p - s] / r0 + dt3 * a.wx[s] * xv[XH + p + s] / r0;
+          acc += dt3 * a.wy[s] * comp(ym, p) / r0 + dt3 * a.wy[s] * comp(yp, p) / r0;
+          acc += dt3 * a.wz[s] * comp(q[R - s], p) / r0 + dt3 * a.wz[s] * comp(q[R + s], p) / r0;
+        }
+        acc += 2.f * dt * m * u / r0 + 0.5f * dt2 * damp * um / r0 +
+               dt3 * (a.wx[0] + a.wy[0] + a.wz[0]) * u / r0;
+        set_comp(o, p, c > 0.f ? acc : 0.f);  // padding columns (c2 = 0) stay zero
+      }
+    } else {
 #pragma unroll
     for (int p = 0; p < 4; ++p) {
       const float b = (comp(bxv, p) + byv) + bzv;
@@ -293,6 +323,7 @@ __device__ __forceinline__ void step_tile(const StepArgs& a, const int t, const 
       } else {
         set_comp(o, p, fmaf(num, inv, u));
       }
+    }
     }
     if (colok) {
       const int64_t at = z * plane + col;
@@ -384,7 +415,7 @@ __device__ __forceinline__ float level_max(const unsigned* arr, int i) {
   return __uint_as_float(m);
 }
 
-template <int R, bool GRAD, int ST, bool DIFF, bool NT>
+template <int R, bool GRAD, int ST, bool DIFF, bool NT, bool BASIC = false>
 __global__ void __launch_bounds__(NTHREADS) step_kernel(const StepArgs a) {
   // Per-level scales of reduced-precision storage: decode cur and prev, choose
   // the encode scales of the level written here from the previous maxima.
@@ -419,7 +450,7 @@ __global__ void __launch_bounds__(NTHREADS) step_kernel(const StepArgs a) {
     return;
   }
   const int t = a.xcd_remap ? remap_tile(bid, a.nstencil_blocks) : bid;
-  step_tile<R, GRAD, ST, DIFF, NT>(a, t, dec_c, dec_p, enc_u, enc_d);
+  step_tile<R, GRAD, ST, DIFF, NT, BASIC>(a, t, dec_c, dec_p, enc_u, enc_d);
 }
 
 // Serving: one launch advances every active shot of one space order by a step.
@@ -659,6 +690,19 @@ hipError_t launch_variant(const StepArgs& a, bool grad, int st, bool diff, bool 
   return hipErrorInvalidValue;
 }
 }  // namespace
+
+hipError_t launch_step_basic(const StepArgs& a, int r, hipStream_t s) {
+  const int nsb = a.samp_out != nullptr ? (a.nsamp + NTHREADS - 1) / NTHREADS : 0;
+  const dim3 grid(a.nstencil_blocks + nsb), block(NTHREADS);
+  switch (r) {
+    case 4: hipLaunchKernelGGL((step_kernel<4, false, ST_F32, false, false, true>), grid, block, 0, s, a); break;
+    case 6: hipLaunchKernelGGL((step_kernel<6, false, ST_F32, false, false, true>), grid, block, 0, s, a); break;
+    case 8: hipLaunchKernelGGL((step_kernel<8, false, ST_F32, false, false, true>), grid, block, 0, s, a); break;
+    case 12: hipLaunchKernelGGL((step_kernel<12, false, ST_F32, false, false, true>), grid, block, 0, s, a); break;
+    default: return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
+}
 
 hipError_t launch_step(const StepArgs& a, int r, bool grad, int st, bool diff, bool nt,
                        hipStream_t s) {
