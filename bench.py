@@ -89,20 +89,25 @@ class Solver:
                           workspace=self.ws, rec_out=self.rec_out)
 
 
-def time_solves(solver, steps, warmup):
+def time_solves(solver, steps, warmup, per_solve=None):
+    """Elapsed seconds of `steps` back-to-back solves (HIP events on the solves'
+    stream) and the host wall time; per_solve, if a list, receives each solve's
+    own event-timed seconds."""
     import torch
     for _ in range(warmup):
         solver.run()
     torch.cuda.synchronize()
-    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(steps + 1)]
     t0 = time.perf_counter()
-    e0.record()
-    for _ in range(steps):
+    ev[0].record()
+    for k in range(steps):
         solver.run()
-    e1.record()
+        ev[k + 1].record()
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
-    return e0.elapsed_time(e1) / 1000.0, wall
+    if per_solve is not None:
+        per_solve.extend(ev[k].elapsed_time(ev[k + 1]) / 1000.0 for k in range(steps))
+    return ev[0].elapsed_time(ev[steps]) / 1000.0, wall
 
 
 def reduced_precision_leg(dev):
@@ -178,23 +183,31 @@ def basic_leg(dev):
     """Ablation after the paper's basic/aggressive experiment (Tables 2-3): the
     forward solve at 256^3 (the sweep's workload) with the unfactorised update
     (every term divided by r0 separately) against the factorised kernel, SO 8-24;
-    throughput and rel-L2 of the basic form's traces against the factorised ones."""
+    throughput and rel-L2 of the basic form's final field against the factorised one
+    (the workload's receivers at z = 20 see no arrival within 500 steps)."""
     import numpy as np
+    import torch
+    from paper_1912_00695_amd import wave
     res = {}
     for so in (8, 12, 16, 24):
         item = {}
-        recs = {}
+        fields = {}
         for name, flag in (("basic", "1"), ("factorised", "0")):
             os.environ["WAVE_BASIC"] = flag
-            S = Solver(c2_problem(so), dev)
+            P = c2_problem(so)
+            S = Solver(P, dev)
             e, _ = time_solves(S, 2, 1)
             item[name + "_gpts"] = round(256 ** 3 * 500 * 2 / e / 1e9, 2)
-            recs[name] = S.rec_out.double().cpu().numpy()
-            del S
+            out = wave.forward(P["grid"], S.vel, S.wav, P["src"], P["rec"], want_final=True,
+                               workspace=S.ws)
+            fields[name] = out["u_final"].double()
+            del S, out
         os.environ.pop("WAVE_BASIC", None)
         item["speedup_factorised_over_basic"] = round(item["factorised_gpts"] / item["basic_gpts"], 3)
-        item["basic_traces_rel_l2_vs_factorised"] = float(
-            np.linalg.norm(recs["basic"] - recs["factorised"]) / np.linalg.norm(recs["factorised"]))
+        item["basic_field_rel_l2_vs_factorised"] = float(
+            torch.linalg.norm(fields["basic"] - fields["factorised"]) /
+            torch.linalg.norm(fields["factorised"]))
+        del fields
         res["so%d" % so] = item
         log("basic vs factorised SO%d: %s" % (so, item))
     return res
@@ -267,8 +280,16 @@ def cpu_baseline(P, target_s=20.0):
     oracle.forward(og, P["vel"], P["wav"][:nsteps], P["src"], P["rec"])
     el = time.perf_counter() - t0
     npts = int(np.prod(P["n"]))
+    cpu = "unknown"
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                cpu = line.split(":", 1)[1].strip()
+                break
+    except OSError:
+        pass
     return {"value": npts * nsteps / el / 1e9, "unit": "Gpt-updates/s",
-            "cores": oracle.num_threads(), "kind": "oracle",
+            "cores": oracle.num_threads(), "kind": "oracle", "cpu_model": cpu,
             "sample": "FP64 oracle, 256^3 SO8 two-layer + 40-cell sponge, source and 256 "
                       "receivers, first %d of the 500 time steps (%.1f s)" % (nsteps, el)}
 
@@ -279,6 +300,10 @@ def main():
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--so", type=int, default=8)
+    ap.add_argument("--n", type=int, default=256,
+                    help="grid points per axis of the timed workload (profiling runs; the "
+                         "benchmark line is quoted at 256)")
+    ap.add_argument("--nt", type=int, default=500, help="time steps of the timed workload")
     ap.add_argument("--no-sweep", action="store_true")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-serving", action="store_true")
@@ -300,12 +325,16 @@ def main():
     dev = torch.device("cuda:0")
     wave.lib()
 
-    P = c2_problem(args.so)
+    if (args.n != 256 or args.nt != 500) and not args.only_timed:
+        print("--n/--nt change the workload: use them with --only-timed", file=sys.stderr)
+        sys.exit(2)
+    P = c2_problem(args.so, nt=args.nt, n=(args.n,) * 3)
     solver = Solver(P, dev)
-    log("timing %d solves of 256^3 SO%d x %d steps (warmup %d)" % (args.steps, args.so,
-                                                                   P["nt"], args.warmup))
-    el, wall = time_solves(solver, args.steps, args.warmup)
-    npts = 256 ** 3
+    log("timing %d solves of %d^3 SO%d x %d steps (warmup %d)" % (args.steps, args.n, args.so,
+                                                                  P["nt"], args.warmup))
+    per_solve = []
+    el, wall = time_solves(solver, args.steps, args.warmup, per_solve)
+    npts = args.n ** 3
     gpts = npts * P["nt"] * args.steps / el / 1e9
     launch_s = el / (args.steps * P["nt"])
     achieved = ALG_BYTES_PER_PT * npts / launch_s / 1e9
@@ -315,11 +344,11 @@ def main():
         "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
         "ms_per_step": round(el / args.steps * 1000.0, 3), "higher_is_better": True,
         "scaling": "weak", "vs_baseline": None, "dtype": "f32", "data": "synthetic",
-        "config": {"workload": "forward solve 256^3 SO%d, two-layer 1500/3000 m/s, 40-cell "
-                               "sponge, 10 Hz Ricker at centre, 256 receivers, 500 steps, "
-                               "dt=0.5*CFL" % args.so,
-                   "grid": [256, 256, 256], "so": args.so, "nt": P["nt"], "nsrc": 1,
-                   "nrec": 256, "storage": "f32"},
+        "config": {"workload": "forward solve %d^3 SO%d, two-layer 1500/3000 m/s, 40-cell "
+                               "sponge, 10 Hz Ricker at centre, %d receivers, %d steps, "
+                               "dt=0.5*CFL" % (args.n, args.so, args.n, P["nt"]),
+                   "grid": [args.n] * 3, "so": args.so, "nt": P["nt"], "nsrc": 1,
+                   "nrec": args.n, "storage": "f32"},
         "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
                      "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
                      "traffic": measured_traffic(),
@@ -328,6 +357,11 @@ def main():
                      "avg_launch_us": round(launch_s * 1e6, 3),
                      "kernel_source_hash": kernel_hash()},
         "wall_s_timed": round(wall, 4),
+        "per_solve": {"median_gpts": round(npts * P["nt"] / sorted(per_solve)[len(per_solve) // 2]
+                                           / 1e9, 2),
+                      "max_gpts": round(npts * P["nt"] / min(per_solve) / 1e9, 2),
+                      "solves": len(per_solve),
+                      "note": "each timed solve on its own (the paper times 5 runs)"},
     }
     del solver
     if args.with_copy:
