@@ -282,15 +282,25 @@ void build_point_tables(const wave_grid* g, const Geom& G, const Tiling& T, cons
 // lies in the extended region of at most two chunks, which sizes its tables).
 bool fused_tiling_ok(const Ctx& C) { return C.L.fused && C.T.zchunk >= C.g->so; }
 
-// Whether a forward solve takes the two-step kernel. Measured on MI355X it wins
-// only where one step's arrays exceed the 256 MiB Infinity Cache and the radius is
-// at most 2 (512^3 SO4: +8 %); where the cache holds the working set (256^3) or at
-// radius 3-4 (160 registers per lane, one 512-thread workgroup per CU) the
-// one-step kernel is faster. WAVE_FUSED=1 forces it (radius <= 4), 0 disables it.
-bool use_fused(const Ctx& C) {
+// Whether an FP32 forward solve without checkpoints takes the two-step kernel, and
+// its z-chunk length. Measured on MI355X (64-plane chunks, cubic grids): it beats
+// the one-step kernel from 448^3 on (SO2 +13..32 %, SO4 +4..17 % at 448-640^3); at
+// 384^3 and below the one-step kernel is faster (its working set is largely served
+// by the 256 MiB Infinity Cache), and at radius 3-4 (139-160 registers per lane,
+// one 512-thread workgroup per CU) it is faster everywhere. Auto: radius <= 2 and
+// at least kFusedMinPoints grid points. WAVE_FUSED=1 forces it (radius <= 4; z-chunks of the
+// one-step policy unless WAVE_F2_ZCHUNK is set), 0 disables it.
+constexpr int64_t kFusedMinPoints = 80000000;
+constexpr int kFusedZChunk = 64;
+bool want_fused(const wave_grid* g, int* zchunk) {
   const int force = env_int("WAVE_FUSED", -1);
+  *zchunk = env_int("WAVE_F2_ZCHUNK", 0);
+  if (store_kind(g) != WAVE_STORE_F32 || g->so / 2 > 4) return false;
   if (force >= 0) return force != 0;
-  return C.g->so / 2 <= 2 && C.nt;
+  const int64_t npts = (int64_t)g->nx * g->ny * g->nz;
+  if (g->so / 2 > 2 || npts < kFusedMinPoints) return false;
+  if (*zchunk == 0) *zchunk = kFusedZChunk;
+  return true;
 }
 
 // Source tables of the two-step kernel: for every tile, the grid points of its
@@ -437,8 +447,8 @@ Blob* build_blob(const Ctx& C, const double* src, int nsrc, const double* rec, i
 
 int setup(Ctx& C, const wave_grid* g, const float* vel, const double* src, int nsrc,
           const double* rec, int nrec, int mode, int ckpt_every, void* ws, size_t ws_bytes,
-          void* stream) {
-  int st = init_ctx(C, g, nsrc, nrec, mode, ckpt_every, ws, ws_bytes, stream);
+          void* stream, int zchunk = 0) {
+  int st = init_ctx(C, g, nsrc, nrec, mode, ckpt_every, ws, ws_bytes, stream, zchunk);
   if (st) return st;
   Blob* B = build_blob(C, src, nsrc, rec, nrec);
   if (hipMemcpyAsync(C.ws + C.L.tables_beg, B->bytes.data(), B->bytes.size(),
@@ -692,17 +702,19 @@ int wave_forward(const wave_grid* g, const float* vel, const float* wavelet,
   if (!points_ok(g, src_xyz_h, nsrc) || !points_ok(g, rec_xyz_h, nrec)) return WAVE_EINVAL;
   if (ckpt != nullptr && ckpt_every <= 0) return WAVE_EINVAL;
   if (ckpt != nullptr && store_kind(g) != WAVE_STORE_F32) return WAVE_EINVAL;
+  // WAVE_BASIC=1: the unfactorised ablation kernel (SO 8, 12, 16, 24; one step per
+  // launch; comparison with the paper's basic/aggressive experiment only)
+  const bool basic = store_kind(g) == WAVE_STORE_F32 && env_int("WAVE_BASIC", 0) != 0;
+  if (basic && g->so != 8 && g->so != 12 && g->so != 16 && g->so != 24) return WAVE_EINVAL;
+  int fz = 0;
+  const bool fused = !basic && ckpt == nullptr && want_fused(g, &fz);
   Ctx C;
   st = setup(C, g, vel, src_xyz_h, nsrc, rec_xyz_h, nrec, WAVE_MODE_FORWARD, 0, workspace,
-             ws_bytes, hip_stream);
+             ws_bytes, hip_stream, fused ? fz : 0);
   if (st) return st;
   if (store_kind(g) != WAVE_STORE_F32)
     return forward_reduced(C, wavelet, nsrc, nrec, rec_out, u0, um1, u_final);
-  // WAVE_BASIC=1: the unfactorised ablation kernel (SO 8, 12, 16, 24; one step per
-  // launch; comparison with the paper's basic/aggressive experiment only)
-  const bool basic = env_int("WAVE_BASIC", 0) != 0;
-  if (basic && g->so != 8 && g->so != 12 && g->so != 16 && g->so != 24) return WAVE_EINVAL;
-  if (!basic && ckpt == nullptr && fused_tiling_ok(C) && use_fused(C))
+  if (fused && fused_tiling_ok(C))
     return forward_fused(C, wavelet, nsrc, nrec, rec_out, u0, um1, u_final);
   float* X[2] = {C.at<float>(C.L.u[0]), C.at<float>(C.L.u[1])};
   HIP_TRY(launch_pack(u0, X[0], C.G, C.s));

@@ -3,9 +3,10 @@ and against the one-step-per-launch path of the same library.
 
 wave_forward can take the two-step path for FP32 storage, radius <= 4, no
 checkpoints and z-chunks of at least 2r planes; by default it does so only where it
-is faster (radius <= 2 on grids beyond the Infinity Cache). These tests force it
-with WAVE_FUSED=1 and select the single-step path with WAVE_FUSED=0 (the variable is
-read at every call). Tolerances: rel-L2 <= 1e-5 against the oracle
+is faster (radius <= 2 on grids of at least 8e7 points, with 64-plane chunks). These
+tests force it with WAVE_FUSED=1 (chunks of the one-step policy, so the small cases
+cross chunk boundaries) and select the single-step path with WAVE_FUSED=0 (the
+variables are read at every call). Tolerances: rel-L2 <= 1e-5 against the oracle
 on traces and final field (FP32 vs FP64), <= 1e-6 between the two GPU paths (both
 evaluate every point's update with the same expression; the bound allows for the
 compiler contracting differently in the two kernels).
@@ -100,8 +101,8 @@ def test_fused_short_runs(nt):
 
 def test_fused_full_size_512_so4_matches_single_step():
     """512^3 SO4, two-layer model with 40-cell sponge, 60 steps: the default path
-    (two-step kernel: radius 2, arrays beyond the Infinity Cache) against the
-    one-step path, which the full-size tests check against the oracle."""
+    (two-step kernel: radius 2, 1.3e8 points, 64-plane chunks) against the one-step
+    path, which the full-size tests check against the oracle."""
     import torch
     from paper_1912_00695_amd import wave
     n, h, nt = (512, 512, 512), (10.0, 10.0, 10.0), 60
