@@ -163,7 +163,8 @@ def two_step_leg(dev):
     (64-plane z-chunks) against one step per launch, on the sweep's 256^3 workload and
     at 512^3 (FP32; 20 algorithmic bytes per point per two-step launch)."""
     res = {}
-    for n, so, nt in ((256, 4, 500), (256, 8, 500), (512, 2, 100), (512, 4, 100), (512, 8, 100)):
+    for n, so, nt in ((256, 4, 500), (256, 8, 500), (512, 2, 100), (512, 4, 100), (512, 6, 100),
+                      (512, 8, 100)):
         item = {}
         for name, flag in (("two_step", "1"), ("one_step", "0")):
             os.environ["WAVE_FUSED"] = flag
@@ -177,8 +178,8 @@ def two_step_leg(dev):
         item["speedup"] = round(item["two_step_gpts"] / item["one_step_gpts"], 3)
         res["%d^3_so%d" % (n, so)] = item
         log("two-step %d^3 SO%d: %s" % (n, so, item))
-    res["default"] = ("two-step kernel used by default for SO <= 4 on grids of at least 8e7 "
-                      "points (64-plane z-chunks)")
+    res["default"] = ("two-step kernel used by default (64-plane z-chunks) for SO2 from 3e7, "
+                      "SO4 from 6e7 and SO6 from 8e7 grid points")
     return res
 
 

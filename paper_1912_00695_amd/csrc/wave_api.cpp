@@ -283,14 +283,15 @@ void build_point_tables(const wave_grid* g, const Geom& G, const Tiling& T, cons
 bool fused_tiling_ok(const Ctx& C) { return C.L.fused && C.T.zchunk >= C.g->so; }
 
 // Whether an FP32 forward solve without checkpoints takes the two-step kernel, and
-// its z-chunk length. Measured on MI355X (64-plane chunks, cubic grids): it beats
-// the one-step kernel from 448^3 on (SO2 +13..32 %, SO4 +4..17 % at 448-640^3); at
-// 384^3 and below the one-step kernel is faster (its working set is largely served
-// by the 256 MiB Infinity Cache), and at radius 3-4 (139-160 registers per lane,
-// one 512-thread workgroup per CU) it is faster everywhere. Auto: radius <= 2 and
-// at least kFusedMinPoints grid points. WAVE_FUSED=1 forces it (radius <= 4; z-chunks of the
-// one-step policy unless WAVE_F2_ZCHUNK is set), 0 disables it.
-constexpr int64_t kFusedMinPoints = 80000000;
+// its z-chunk length. Measured on MI355X (64-plane chunks, cubic grids, two-step vs
+// one-step): SO2 -5 % at 256^3, +12 % at 320^3, +37 % at 512^3; SO4 -8 % at 256^3,
+// -2 % at 384^3, +9 % at 416^3, +24 % at 512^3; SO6 -2 % at 416^3, +9 % at 448^3,
+// +12 % at 512^3; SO8 (158 registers per lane, one 512-thread workgroup per CU) -6 %
+// at 512^3. Below these sizes the one-step kernel's working set is largely served by
+// the 256 MiB Infinity Cache. Auto: radius r <= 3 and at least kFusedMinPoints[r]
+// grid points. WAVE_FUSED=1 forces it (radius <= 4; z-chunks of the one-step policy
+// unless WAVE_F2_ZCHUNK is set), 0 disables it.
+constexpr int64_t kFusedMinPoints[4] = {0, 30000000, 60000000, 80000000};
 constexpr int kFusedZChunk = 64;
 bool want_fused(const wave_grid* g, int* zchunk) {
   const int force = env_int("WAVE_FUSED", -1);
@@ -298,7 +299,7 @@ bool want_fused(const wave_grid* g, int* zchunk) {
   if (store_kind(g) != WAVE_STORE_F32 || g->so / 2 > 4) return false;
   if (force >= 0) return force != 0;
   const int64_t npts = (int64_t)g->nx * g->ny * g->nz;
-  if (g->so / 2 > 2 || npts < kFusedMinPoints) return false;
+  if (g->so / 2 > 3 || npts < kFusedMinPoints[g->so / 2]) return false;
   if (*zchunk == 0) *zchunk = kFusedZChunk;
   return true;
 }

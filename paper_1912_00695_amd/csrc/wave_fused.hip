@@ -51,6 +51,14 @@ __device__ __forceinline__ void fused2_tile(const Fused2Args& f, const int t) {
   __shared__ float4 vlds[EY * F2_EX4];
   __shared__ float4 inj[EY * F2_EX4];
   __shared__ float bzs[MAXZCHUNK + 2 * F2_XH];
+  // Per-thread slots (written and read by the same thread, no barrier needed) for
+  // R+1 planes: the u^n ring item of planes za+1 .. za+1+R, loaded in the same
+  // iteration as the neighbouring workgroups load those columns as their queue
+  // heads (so the ring is served by L2); and c2 of the tile columns at planes
+  // za-R .. za for stage B (stage A's own load, reused).
+  __shared__ float4 ringbuf[R + 1][NRING];
+  __shared__ float4 cring[R + 1][TY * NTX];
+  const auto slot = [](const int z) { return ((z % (R + 1)) + (R + 1)) % (R + 1); };
 
   const int tx_t = t % a.ntile_x;
   const int rest = t / a.ntile_x;
@@ -108,19 +116,28 @@ __device__ __forceinline__ void fused2_tile(const Fused2Args& f, const int t) {
   // Prologue: u^n queue for za0 (planes za0-R .. za0+R), the LDS copy of plane za0,
   // prev and c2 at za0, c2 at the first stage-B plane.
   float4 q[2 * R + 1], vq[2 * R + 1];
-  f4v up, cc, ccb;
+  f4v up, cc;
   {
     f4v qr[2 * R + 1];
 #pragma unroll
     for (int s = 0; s <= 2 * R; ++s) qr[s] = ld(a.cur, za0 - R + s, true, vo);
-    const f4v hr = ld(a.cur, za0, true, vo_h);
+    const f4v hr0 = ld(a.cur, za0, true, vo_h);
     up = ld(a.prev, za0, true, vo);
     cc = ld(a.c2, za0, true, vo);
-    ccb = ld(a.c2, za0 - R, za0 - R >= z0, vo);
 #pragma unroll
     for (int s = 0; s <= 2 * R; ++s) q[s] = W(qr[s]);
     if (act) ulds[0][(ey + R) * F2_UROW4 + ex + F2_XH4] = q[R];
-    if (hl >= 0) ulds[0][hl] = W(hr);
+    if (hl >= 0) ulds[0][hl] = W(hr0);
+  }
+  {
+    // ring items of planes za0+1 .. za0+R into their slots
+    f4v hr[R];
+#pragma unroll
+    for (int j = 0; j < R; ++j) hr[j] = ld(a.cur, za0 + 1 + j, true, vo_h);
+    if (hl >= 0) {
+#pragma unroll
+      for (int j = 0; j < R; ++j) ringbuf[slot(za0 + 1 + j)][tid] = W(hr[j]);
+    }
   }
 #pragma unroll
   for (int s = 0; s <= 2 * R; ++s) vq[s] = zero4;
@@ -224,17 +241,18 @@ __device__ __forceinline__ void fused2_tile(const Fused2Args& f, const int t) {
 
   const int crowA = (ey + R) * F2_UROW4 + ex + F2_XH4;
   const int crowB = ey * F2_EX4 + ex;
-  const int slotB = (ey - R) * NTX + (ex - F2_XH4);  // tile layout (TX floats per row)
+  // tile-layout slot of an inner thread (TX floats per row); 0 for the others, which
+  // read a valid slot but store nothing
+  const int slotB = inner ? (ey - R) * NTX + (ex - F2_XH4) : 0;
 
   auto plane_step = [&](const int za, const int buf) {
     const int zb = za - R;
     const bool moreA = za + 1 < za1;
     // Loads for the next plane.
     const f4v nq = ld(a.cur, za + 1 + R, moreA, vo);
-    const f4v nh = ld(a.cur, za + 1, moreA, vo_h);
+    const f4v nh = ld(a.cur, za + 1 + R, za + 1 + R < za1, vo_h);  // ring, R planes ahead
     const f4v nup = ld(a.prev, za + 1, moreA, vo);
     const f4v ncc = ld(a.c2, za + 1, moreA, vo);
-    const f4v ncb = ld(a.c2, zb + 1, zb + 1 >= z0 && zb + 1 < z1, inner ? vo : kOOB);
 
     // Stage A: v = u^{n+1} at plane za on E.
     float lap[4];
@@ -244,7 +262,9 @@ __device__ __forceinline__ void fused2_tile(const Fused2Args& f, const int t) {
           inject(f.eent, f.ecsr_idx, f.ecsr_w, f.etrace_row, ea, ea_end, eza, act, tid);
       lap[0] += iv.x; lap[1] += iv.y; lap[2] += iv.z; lap[3] += iv.w;
     }
-    const float4 v = update(q[R], W(up), W(cc), bzs[za - za0], lap);
+    const float4 ccv = W(cc);
+    if (inner) cring[slot(za)][slotB] = ccv;  // c2 at za for stage B, R planes later
+    const float4 v = update(q[R], W(up), ccv, bzs[za - za0], lap);
     // stores on every path: planes outside the chunk get a resource with no
     // records, lanes outside the tile or the grid an out-of-range offset
     Store<ST_F32>::template stb<NT>(rs(a.out, za, za >= z0 && za < z1), inner ? vo : kOOB, v);
@@ -265,22 +285,22 @@ __device__ __forceinline__ void fused2_tile(const Fused2Args& f, const int t) {
             inject(a.ent, a.csr_idx, a.csr_w, a.trace_row, eb, eb_end, ezb, inner, slotB);
         lapb[0] += iv.x; lapb[1] += iv.y; lapb[2] += iv.z; lapb[3] += iv.w;
       }
-      w = update(vq[R], q[0], W(ccb), bzs[max(zb - za0, 0)], lapb);
+      w = update(vq[R], q[0], cring[slot(zb)][slotB], bzs[max(zb - za0, 0)], lapb);
     }
     Store<ST_F32>::template stb<NT>(rs(f.out2, zb, doB), inner ? vo : kOOB, w);
 
     // Stage plane za+1 of u^n into the other LDS buffer.
     if (moreA) {
       if (act) ulds[buf ^ 1][crowA] = q[R + 1];
-      if (hl >= 0) ulds[buf ^ 1][hl] = W(nh);
+      if (hl >= 0) ulds[buf ^ 1][hl] = ringbuf[slot(za + 1)][tid];
     }
+    if (hl >= 0 && za + 1 + R < za1) ringbuf[slot(za + 1 + R)][tid] = W(nh);
     __syncthreads();
 #pragma unroll
     for (int s = 0; s < 2 * R; ++s) q[s] = q[s + 1];
     q[2 * R] = W(nq);
     up = nup;
     cc = ncc;
-    ccb = ncb;
   };
   int za = za0;
   for (; za + 1 < za1; za += 2) {

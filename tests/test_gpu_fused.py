@@ -3,7 +3,7 @@ and against the one-step-per-launch path of the same library.
 
 wave_forward can take the two-step path for FP32 storage, radius <= 4, no
 checkpoints and z-chunks of at least 2r planes; by default it does so only where it
-is faster (radius <= 2 on grids of at least 8e7 points, with 64-plane chunks). These
+is faster (SO2/4/6 from 3e7/6e7/8e7 grid points, with 64-plane chunks). These
 tests force it with WAVE_FUSED=1 (chunks of the one-step policy, so the small cases
 cross chunk boundaries) and select the single-step path with WAVE_FUSED=0 (the
 variables are read at every call). Tolerances: rel-L2 <= 1e-5 against the oracle
