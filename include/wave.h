@@ -123,6 +123,15 @@ size_t wave_checkpoint_bytes(const wave_grid* g, int ckpt_every);
  * With 16-bit storage the levels are rounded to the storage format after every
  * step (the error against FP32 storage is a property of the format; the FP32
  * arithmetic is unchanged).
+ * Execution: one launch per step, or, for FP32 storage without checkpoints on
+ * large grids (SO2 from 3e7, SO4 from 6e7, SO6 from 8e7 points), two fused steps
+ * per launch (temporal blocking); both evaluate every point's update with the same
+ * expression. For FP32 storage at SO <= 8 the forward workspace holds two extra
+ * levels for that kernel. Environment (tuning and ablation, read at every call):
+ * WAVE_FUSED=0/1 disables/forces the two-step kernel (SO <= 8); WAVE_BASIC=1 runs
+ * the unfactorised update of the paper's SO2 listing (SO 8, 12, 16, 24 only, else
+ * WAVE_EINVAL); WAVE_ZCHUNK, WAVE_F2_ZCHUNK, WAVE_NT, WAVE_XCD_REMAP override the
+ * z-chunk length, non-temporal streams and block order.
  * Returns WAVE_OK or a negative status. */
 int wave_forward(const wave_grid* g, const float* vel, const float* wavelet,
                  const double* src_xyz_h, int nsrc, const double* rec_xyz_h, int nrec,

@@ -129,3 +129,29 @@ def test_fused_full_size_512_so4_matches_single_step():
     print("  traces %.3e  field %.3e" % (rel_l2(r1, r0), rel_l2(u1, u0)), flush=True)
     assert np.abs(r0).max() > 0
     assert rel_l2(r1, r0) <= 1e-6 and rel_l2(u1, u0) <= 1e-6
+
+
+def test_fused_full_size_512_so4_matches_oracle():
+    """The default path at 512^3 SO4 (two-step kernel, 64-plane chunks) against the
+    FP64 oracle: 40 steps, a source off the tile and chunk grid, receivers on a line
+    through it and scattered points near it; traces and the final field."""
+    import torch
+    import oracle
+    from paper_1912_00695_amd import wave
+    n, h, nt = (512, 512, 512), (10.0, 10.0, 10.0), 40
+    vel = inputs.smooth_random_range(n, 1500.0, 3000.0, 20.0, seed=71)
+    c = Case(n, h, 4, nt, vel, 3000.0, nbl=(40,) * 6)
+    c.src = np.array([[2560.5, 2551.0, 2561.7]])
+    c.wavelet = inputs.ricker(15.0, c.dt, nt)[:, None]
+    c.rec = np.concatenate([inputs.line_x(n, h, 255, 257), c.src + 25.0])
+    print("512^3 SO4 default path vs oracle (%d threads)" % oracle.num_threads(), flush=True)
+    os.environ.pop("WAVE_FUSED", None)
+    dev = torch.device("cuda:0")
+    t = lambda a: torch.from_numpy(np.ascontiguousarray(a, dtype=np.float32)).to(dev)
+    o = wave.forward(c.wgrid(), t(c.vel), t(c.wavelet), c.src, c.rec, want_final=True)
+    rec, uf = o["rec"].cpu().numpy(), o["u_final"].cpu().numpy()
+    del o
+    orec, ouf, _ = c.oracle_forward()
+    er, eu = rel_l2(rec, orec), rel_l2(uf, ouf)
+    print("  traces %.3e  field %.3e" % (er, eu), flush=True)
+    assert np.abs(orec).max() > 0 and er <= 1e-5 and eu <= 1e-5
