@@ -217,6 +217,60 @@ def basic_leg(dev):
     return res
 
 
+def adjoint_gradient_leg(dev):
+    """The gradient workload: 256^3 SO8, two-layer background with 40-cell sponge,
+    10 Hz Ricker at (128, 128, 20), 65,536 receivers on the plane z = 20, 800 steps,
+    checkpoints every 50. Times the forward solve that writes the checkpoints, one
+    adjoint solve, the gradient given the checkpoints (segment recompute + adjoint
+    with accumulation) and the RTM image (same pass, imaging condition); seeded random
+    data for the adjoint-driven passes. Algorithmic bytes per point and step: adjoint
+    16; gradient / image 44 (recomputed forward step 16, adjoint step 16, stored level
+    4, accumulator read and write 8)."""
+    import numpy as np
+    import torch
+    from paper_1912_00695_amd import inputs, wave
+    n, h, nt, C = (256, 256, 256), (10.0, 10.0, 10.0), 800, 50
+    dt = 0.5 * wave.cfl_dt_max(8, 3000.0, h)
+    g = wave.make_grid(n, h, 8, dt, nt, (40,) * 6, vmax=3000.0)
+    vel = torch.from_numpy(inputs.two_layer(n, 1500.0, 3000.0, 128)).to(dev)
+    wav = torch.from_numpy(inputs.ricker(10.0, dt, nt)[:, None]).to(dev)
+    src = inputs.point((128, 128, 20), h)
+    rec = inputs.plane_z(n, h, 20)
+    d = torch.from_numpy(np.random.default_rng(3).standard_normal(
+        (nt, len(rec))).astype(np.float32)).to(dev)
+    npts = 256 ** 3
+    res = {}
+
+    def timed(fn, reps=2):
+        fn()
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for _ in range(reps):
+            out = fn()
+        e1.record()
+        torch.cuda.synchronize()
+        return e0.elapsed_time(e1) / 1000.0 / reps, out
+
+    t, fw = timed(lambda: wave.forward(g, vel, wav, src, rec, ckpt_every=C))
+    ck = fw["ckpt"]
+    res["forward_with_checkpoints"] = {"gpts": round(npts * nt / t / 1e9, 2), "ms": round(t * 1e3, 2)}
+    del fw
+    t, _ = timed(lambda: wave.adjoint(g, vel, d, rec, src))
+    res["adjoint"] = {"gpts": round(npts * nt / t / 1e9, 2), "ms": round(t * 1e3, 2),
+                      "hbm_frac_16B": round(npts * nt * 16 / t / 8e12, 4)}
+    t, _ = timed(lambda: wave.gradient(g, vel, wav, src, rec, d, ckpt=ck, ckpt_every=C))
+    res["gradient_given_checkpoints"] = {"gpts": round(npts * nt / t / 1e9, 2),
+                                         "ms": round(t * 1e3, 2),
+                                         "hbm_frac_44B": round(npts * nt * 44 / t / 8e12, 4)}
+    t, _ = timed(lambda: wave.rtm(g, vel, wav, src, rec, d, ckpt=ck, ckpt_every=C))
+    res["rtm_given_checkpoints"] = {"gpts": round(npts * nt / t / 1e9, 2), "ms": round(t * 1e3, 2),
+                                    "hbm_frac_44B": round(npts * nt * 44 / t / 8e12, 4)}
+    del ck
+    log("adjoint/gradient C3: %s" % res)
+    return res
+
+
 def serving_leg(dev, nreq):
     """The serving workload: Poisson arrivals at 20/s (seed 5) of forward shots drawn
     from {96^3, 128^3, 192^3, 256^3, 160x160x320} x SO {4, 8} x nt in [200, 1000],
@@ -405,6 +459,7 @@ def main():
         out["lowp_512_so8"] = reduced_precision_leg(dev)
         out["two_step_kernel"] = two_step_leg(dev)
         out["basic_vs_factorised_256"] = basic_leg(dev)
+        out["adjoint_gradient_c3"] = adjoint_gradient_leg(dev)
     if not args.no_serving:
         out["serving"] = serving_leg(dev, args.serving_requests)
     if not args.no_cpu:
