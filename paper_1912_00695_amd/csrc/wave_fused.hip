@@ -310,8 +310,13 @@ __device__ __forceinline__ void fused2_tile(const Fused2Args& f, const int t) {
   if (za < za1) plane_step(za, 0);
 }
 
+#ifndef WAVE_F2_WPE
+#define WAVE_F2_WPE 1
+#endif
 template <int R, bool NT>
-__global__ void __launch_bounds__(F2_THREADS) fused2_kernel(const Fused2Args f) {
+__global__ void __launch_bounds__(F2_THREADS)
+__attribute__((amdgpu_waves_per_eu(R >= 3 ? WAVE_F2_WPE : 1)))
+fused2_kernel(const Fused2Args f) {
   const StepArgs& a = f.a;
   const int bid = blockIdx.x;
   if (bid >= a.nstencil_blocks) {
