@@ -72,30 +72,36 @@ int env_int(const char* name, int dflt) {
   return std::atoi(s);
 }
 
-// z-chunking: aim at ~512 workgroups (two per CU) with chunks of 8..32 planes.
-// Longer chunks amortise the 2r planes each chunk re-reads to prime its z queue;
-// measured on MI355X at 256^3 SO8, 32-plane chunks beat 16 (1024 workgroups) by
-// ~10 % and 48/64 lose to load imbalance and low occupancy. WAVE_ZCHUNK overrides
-// the chunk length (tuning sweeps).
-Tiling make_tiling(const Geom& G, int zchunk) {
+// z-chunking: floor(512 / tiles per plane) chunks (at least one, of at least 8
+// planes): about 512 workgroups, two per CU, all resident at once, each sweeping one
+// long chunk. Measured on MI355X at SO8, among the chunk lengths tried: 256^3 best at
+// 32 planes (512 workgroups), 384^3 at 128 (432), 448^3 at 224 (392), 512^3 at 256
+// (512). More workgroups at once (576-1024) lost 5-15 %, several rounds of short
+// chunks (the previous policy for large grids: 20 planes) lost 3-6 % at SO8, fewer
+// than ~400 workgroups leave CUs idle. Long chunks also amortise the 2r planes each
+// chunk re-reads to prime its z queue, so the gain grows with the order (512^3 over
+// 20-plane chunks: +5 % SO8, +11 % SO16, +23 % SO24; FP32 and the 16-bit difference
+// form). The naive 16-bit form (short_chunks) keeps chunks of 8..32 planes for about
+// 512 workgroups, and balanced chunks of about 20 planes, swept in several rounds,
+// for grids that would need more than 1024 workgroups at 32 planes: 546 Gpt/s at
+// 512^3 SO8 against 498 with one long chunk per workgroup. WAVE_ZCHUNK overrides the
+// chunk length (tuning sweeps).
+Tiling make_tiling(const Geom& G, int zchunk, bool short_chunks) {
   Tiling T;
   T.ntile_x = (G.nx + TX - 1) / TX;
   T.ntile_y = (G.ny + TY - 1) / TY;
   const int bxy = T.ntile_x * T.ntile_y;
   int zc = zchunk > 0 ? zchunk : env_int("WAVE_ZCHUNK", 0);
-  if (zc <= 0) {
-    // about 512 workgroups (two per CU) with chunks of 8..32 planes
+  if (zc <= 0 && short_chunks) {
     const int want = std::max(1, (512 + bxy - 1) / bxy);
-    zc = (G.nz + want - 1) / want;
-    zc = std::min(std::max(zc, 8), 32);
-    // Grids that need more than 1024 workgroups at 32-plane chunks run in several
-    // rounds of resident workgroups: balanced chunks of about 20 planes keep the
-    // planes swept at once within the caches (measured on MI355X: +7-10 % at 384^3
-    // and 512^3 over 32-plane chunks; 256^3 stays at 32).
+    zc = std::min(std::max((G.nz + want - 1) / want, 8), 32);
     if ((int64_t)bxy * ((G.nz + 31) / 32) > 1024) {
       const int nch = (G.nz + 19) / 20;
       zc = (G.nz + nch - 1) / nch;
     }
+  } else if (zc <= 0) {
+    const int nch = std::max(1, 512 / bxy);
+    zc = std::max((G.nz + nch - 1) / nch, 8);
   }
   zc = std::max(1, std::min({zc, G.nz, MAXZCHUNK}));
   T.zchunk = zc;
@@ -398,7 +404,7 @@ int init_ctx(Ctx& C, const wave_grid* g, int nsrc, int nrec, int mode, int ckpt_
              size_t ws_bytes, void* stream, int zchunk) {
   C.g = g;
   C.G = make_geom(g);
-  C.T = make_tiling(C.G, zchunk);
+  C.T = make_tiling(C.G, zchunk, store_kind(g) != WAVE_STORE_F32 && !store_diff(g));
   C.L = make_layout(g, nsrc, nrec, mode, ckpt_every);
   if (ws == nullptr || (reinterpret_cast<uintptr_t>(ws) % kAlign) != 0) return WAVE_EINVAL;
   if (ws_bytes < C.L.total) return WAVE_ENOMEM;

@@ -68,7 +68,7 @@ int validate(const wave_grid* g);  // grid_ok + stability limit
 bool points_ok(const wave_grid* g, const double* xyz, int np);
 Geom make_geom(const wave_grid* g);
 // zchunk > 0 fixes the z-chunk length; 0 applies the single-solve policy
-Tiling make_tiling(const Geom& G, int zchunk = 0);
+Tiling make_tiling(const Geom& G, int zchunk = 0, bool short_chunks = false);
 Layout make_layout(const wave_grid* g, int nsrc, int nrec, int mode, int ckpt_every);
 // geometry, tiling, layout and weights of a call on workspace ws (no device work)
 int init_ctx(Ctx& C, const wave_grid* g, int nsrc, int nrec, int mode, int ckpt_every, void* ws,

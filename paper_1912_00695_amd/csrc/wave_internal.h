@@ -16,7 +16,7 @@ constexpr int VX = 4;
 constexpr int NTX = TX / VX;     // threads along x
 constexpr int NTHREADS = NTX * TY;
 constexpr int MAXR = 12;         // SO <= 24
-constexpr int MAXZCHUNK = 64;    // planes per z-chunk at most
+constexpr int MAXZCHUNK = 256;   // planes per z-chunk at most (<= NTHREADS)
 constexpr int SAMPLE_THREADS = 256;
 
 // Pitched field geometry: rows padded to a multiple of 32 floats (128 bytes);

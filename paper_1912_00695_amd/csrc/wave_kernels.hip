@@ -71,7 +71,10 @@ __device__ __forceinline__ void step_tile(const StepArgs& a, const int t, const 
   // of a step is resident at once. With non-temporal streams (grids whose step
   // does not fit the Infinity Cache, swept in several rounds of workgroups) it
   // ranged from +1 % to -8 % and is off.
-  constexpr bool HRG = halo_ring(R) && !NT;
+#ifndef WAVE_HRING_NT
+#define WAVE_HRING_NT 0
+#endif
+  constexpr bool HRG = halo_ring(R) && (!NT || WAVE_HRING_NT);
   using Raw = typename Store<ST>::Raw;
   __shared__ Raw hbuf[HRG ? R + 1 : 1][HRG ? NH : 1];
   const auto hslot = [](const int p) { return p % (R + 1); };  // p >= 0
