@@ -10,11 +10,11 @@
 //     tables on an upload stream while resident shots keep running (host-pageable
 //     copies block the calling thread, so they stay off the thread that feeds
 //     the GPU);
-//   * resident shots of each space order advance together: a captured graph of
-//     kReplaySteps launches of the batched step kernel per space order is
-//     replayed; per-shot step counters live in device memory, so one graph serves
-//     any mix of shots at any step, and is re-captured only when the set of
-//     resident shots changes;
+//   * resident shots advance in groups (one space order, per-step arrays that fit
+//     the Infinity Cache together): a captured graph of kReplaySteps launches of
+//     the batched step kernel per group, group after group, is replayed; per-shot
+//     step counters live in device memory, so one graph serves any mix of shots at
+//     any step, and is re-captured only when the set of resident shots changes;
 //   * the graph is launched several times back to back (about kSyncWork of
 //     estimated GPU time) before the worker reads the counters back, retires
 //     finished shots (traces copied to the caller's host buffer, pool space
@@ -29,7 +29,6 @@
 #include <condition_variable>
 #include <cstring>
 #include <deque>
-#include <map>
 #include <memory>
 #include <mutex>
 #include <thread>
@@ -44,10 +43,14 @@
 namespace wave {
 namespace {
 
-constexpr int kReplaySteps = 16;    // launches per space order in one captured graph (even)
+constexpr int kReplaySteps = 16;    // launches per group in one captured graph (even)
 constexpr double kSyncWork = 2e-3;  // GPU seconds of work enqueued between host syncs
 constexpr double kUpdateRate = 250e9;  // grid-point updates per second, for that estimate
 constexpr int kEngineZChunk = 32;      // z-chunk length of resident shots
+// Shots stepped together in one run of kReplaySteps launches: their per-step arrays
+// (two levels and v^2 dt^2) fit the 256 MB Infinity Cache together, so they stay
+// cache-resident across the run's steps. WAVE_ENGINE_GROUP_MB overrides (tests).
+constexpr size_t kCacheGroupBytes = (size_t)224 << 20;
 
 double now_s() {
   using namespace std::chrono;
@@ -435,21 +438,39 @@ class Engine {
     return WAVE_OK;
   }
 
-  // Tables of (shot, tile) per space order, and the captured replay graph.
+  // Tables of (shot, tile) per group, and the captured replay graph. A group holds
+  // shots of one space order whose per-step arrays fit the Infinity Cache together
+  // (first fit in admission order); the graph runs kReplaySteps launches of each
+  // group back to back, so a group's fields are re-read from the cache on every
+  // step of its run rather than streamed from HBM with every other resident shot's.
   int rebuild_graph(const std::vector<Shot*>& active) {
-    std::map<int, std::vector<BatchEntry>> groups;  // radius -> entries
+    struct Group {
+      int r;
+      size_t bytes;
+      std::vector<BatchEntry> e;
+    };
+    const char* env = std::getenv("WAVE_ENGINE_GROUP_MB");
+    const size_t cap = env != nullptr && std::atoi(env) > 0 ? (size_t)std::atoi(env) << 20
+                                                            : kCacheGroupBytes;
+    std::vector<Group> groups;
     std::vector<int> slots;
     for (Shot* s : active) {
       slots.push_back(s->slot);
-      auto& v = groups[s->g.so / 2];
-      for (int t = 0; t < s->C.T.nblocks; ++t) v.push_back(BatchEntry{s->slot, t});
-      for (int k = 0; k < s->nsamp_blocks; ++k) v.push_back(BatchEntry{s->slot, -1 - k});
+      const int r = s->g.so / 2;
+      const size_t b = (size_t)s->C.G.nfield * 12;  // two FP32 levels and v^2 dt^2
+      size_t gi = 0;
+      while (gi < groups.size() && (groups[gi].r != r || groups[gi].bytes + b > cap)) ++gi;
+      if (gi == groups.size()) groups.push_back(Group{r, 0, {}});
+      Group& G = groups[gi];
+      G.bytes += b;
+      for (int t = 0; t < s->C.T.nblocks; ++t) G.e.push_back(BatchEntry{s->slot, t});
+      for (int k = 0; k < s->nsamp_blocks; ++k) G.e.push_back(BatchEntry{s->slot, -1 - k});
     }
     std::vector<BatchEntry> all;
     std::vector<std::pair<int, std::pair<int, int>>> segs;  // radius, (offset, count)
-    for (auto& kv : groups) {
-      segs.push_back({kv.first, {(int)all.size(), (int)kv.second.size()}});
-      all.insert(all.end(), kv.second.begin(), kv.second.end());
+    for (auto& G : groups) {
+      segs.push_back({G.r, {(int)all.size(), (int)G.e.size()}});
+      all.insert(all.end(), G.e.begin(), G.e.end());
     }
     if ((int)all.size() > table_cap_) return WAVE_ENOMEM;
     cur_table_ ^= 1;
@@ -462,12 +483,10 @@ class Engine {
     hipGraph_t graph = nullptr;
     HIP_TRY(hipStreamBeginCapture(s_exec_, hipStreamCaptureModeThreadLocal));
     hipError_t err = hipSuccess;
-    for (int k = 0; k < kReplaySteps && err == hipSuccess; ++k)
-      for (auto& sg : segs) {
+    for (auto& sg : segs)
+      for (int k = 0; k < kReplaySteps && err == hipSuccess; ++k)
         err = launch_batched(d_desc_, tab + sg.second.first, sg.second.second, sg.first, k & 1,
                              s_exec_);
-        if (err != hipSuccess) break;
-      }
     hipError_t e2 = hipStreamEndCapture(s_exec_, &graph);
     if (err != hipSuccess || e2 != hipSuccess) {
       if (graph) (void)hipGraphDestroy(graph);
