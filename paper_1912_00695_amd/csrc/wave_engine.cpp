@@ -405,8 +405,7 @@ class Engine {
     float* U1 = s->C.at<float>(s->C.L.u[1]);
     // the velocity is staged in u[1] (dense fits in pitched), turned into c2, then
     // both u levels are cleared
-    HIP_TRY(hipMemcpyAsync(base + s->C.L.tables_beg, s->blob->bytes.data(), s->blob->bytes.size(),
-                           hipMemcpyHostToDevice, s_up_));
+    HIP_TRY(upload_blob(*s->blob, base + s->C.L.tables_beg, s_up_));
     HIP_TRY(hipMemcpyAsync(U1, s->vel.data(), s->vel.size() * sizeof(float),
                            hipMemcpyHostToDevice, s_up_));
     HIP_TRY(launch_prep_c2(U1, s->C.at<float>(s->C.L.c2), s->C.G, g->dt, s_up_));

@@ -4,6 +4,8 @@
 
 #include <hip/hip_runtime.h>
 
+#include <memory>
+#include <utility>
 #include <vector>
 
 #include "../../include/wave.h"
@@ -35,13 +37,22 @@ struct Layout {
   size_t total;
 };
 
-// Host image of the table region, uploaded with one copy.
+// Host image of the table region. Allocated uninitialised (the point tables are
+// sized for 8 corners per point, most of it unused for on-grid points); the
+// builders record the ranges they write, and only those are uploaded.
 struct Blob {
-  std::vector<char> bytes;
-  size_t base;
+  std::unique_ptr<char[]> bytes;
+  size_t base = 0;
+  std::vector<std::pair<size_t, size_t>> used;  // (offset from base, bytes)
   template <class T>
-  T* at(size_t off) { return reinterpret_cast<T*>(bytes.data() + (off - base)); }
+  T* at(size_t off) { return reinterpret_cast<T*>(bytes.get() + (off - base)); }
+  void mark(size_t off, size_t n) {
+    if (n > 0) used.push_back({off - base, n});
+  }
 };
+// Enqueue the upload of b's written ranges into the table region at dst (the
+// device address of the region's start).
+hipError_t upload_blob(const Blob& b, char* dst, hipStream_t s);
 
 // Per-call state.
 struct Ctx {
