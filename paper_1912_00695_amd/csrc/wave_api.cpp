@@ -291,6 +291,8 @@ void build_point_tables(const wave_grid* g, const Geom& G, const Tiling& T, cons
     en.local = h.local;
     en.csr_beg = (int)a;
     en.csr_end = (int)b;
+    en.tidx = b - a == 1 ? h.p : -1;
+    en.w = b - a == 1 ? h.w : 0.f;
     ent[e++] = en;
     tile_beg[h.tile + 1]++;
     a = b;
@@ -397,6 +399,8 @@ void build_ext_tables(const wave_grid* g, const Geom& G, const Tiling& T, int r,
       ++c;
     }
     en.csr_end = c;
+    en.tidx = c - en.csr_beg == 1 ? cidx[en.csr_beg] : -1;
+    en.w = c - en.csr_beg == 1 ? cw[en.csr_beg] : 0.f;
     ent[e] = en;
     tile_beg[kv.first.tile + 1]++;
     ++e;

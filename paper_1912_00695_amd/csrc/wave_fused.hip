@@ -152,15 +152,22 @@ __device__ __forceinline__ void fused2_tile(const Fused2Args& f, const int t) {
   // tile (stage B); eza / ezb hold the plane of the next group of each, so the
   // per-plane tests need no load.
   int ea = 0, ea_end = 0, eb = 0, eb_end = 0, eza = INT_MAX, ezb = INT_MAX;
+  int ega = 0, egb = 0;  // ends of the groups at planes eza, ezb
   if (f.etile_beg != nullptr) {
     ea = f.etile_beg[t];
     ea_end = f.etile_beg[t + 1];
-    if (ea < ea_end) eza = f.eent[ea].z;
+    if (ea < ea_end) {
+      eza = f.eent[ea].z;
+      ega = f.eent[ea].grp_end;
+    }
   }
   if (a.tile_beg != nullptr) {
     eb = a.tile_beg[t];
     eb_end = a.tile_beg[t + 1];
-    if (eb < eb_end) ezb = a.ent[eb].z;
+    if (eb < eb_end) {
+      ezb = a.ent[eb].z;
+      egb = a.ent[eb].grp_end;
+    }
   }
 
   // Laplacian of four consecutive points from a z-queue and an LDS plane (row
@@ -216,16 +223,20 @@ __device__ __forceinline__ void fused2_tile(const Fused2Args& f, const int t) {
     }
     return o;
   };
-  // Scatter one plane's injection entries [e, ge) into inj and return the
-  // thread's four values at float4 slot `slot` (cleared after); advance e and the
-  // next group's plane ez.
+  // Scatter one plane's injection entries [e, eg) into inj and return the
+  // thread's four values at float4 slot `slot` (cleared after); advance e to the
+  // next group, with its plane ez and end eg.
   auto inject = [&](const InjEntry* ent, const int* cidx, const float* cw, const float* row,
-                    int& e, const int e_end, int& ez, const bool mine, const int slot) {
-    const int ge = ent[e].grp_end;
-    for (int i = e + tid; i < ge; i += F2_THREADS) {
+                    int& e, const int e_end, int& ez, int& eg, const bool mine,
+                    const int slot) {
+    for (int i = e + tid; i < eg; i += F2_THREADS) {
       const InjEntry en = ent[i];
       float s = 0.f;
-      for (int c = en.csr_beg; c < en.csr_end; ++c) s = fmaf(cw[c], row[cidx[c]], s);
+      if (en.tidx >= 0) {  // single term, carried in the entry
+        s = fmaf(en.w, row[en.tidx], 0.f);
+      } else {
+        for (int c = en.csr_beg; c < en.csr_end; ++c) s = fmaf(cw[c], row[cidx[c]], s);
+      }
       reinterpret_cast<float*>(inj)[en.local] = s;
     }
     __syncthreads();
@@ -234,8 +245,12 @@ __device__ __forceinline__ void fused2_tile(const Fused2Args& f, const int t) {
       iv = inj[slot];
       inj[slot] = zero4;
     }
-    e = ge;
-    ez = e < e_end ? ent[e].z : INT_MAX;
+    e = eg;
+    ez = INT_MAX;
+    if (e < e_end) {
+      ez = ent[e].z;
+      eg = ent[e].grp_end;
+    }
     return iv;
   };
 
@@ -259,7 +274,7 @@ __device__ __forceinline__ void fused2_tile(const Fused2Args& f, const int t) {
     laplacian(q, ulds[buf], crowA, F2_UROW4, lap);
     if (za == eza) {
       const float4 iv =
-          inject(f.eent, f.ecsr_idx, f.ecsr_w, f.etrace_row, ea, ea_end, eza, act, tid);
+          inject(f.eent, f.ecsr_idx, f.ecsr_w, f.etrace_row, ea, ea_end, eza, ega, act, tid);
       lap[0] += iv.x; lap[1] += iv.y; lap[2] += iv.z; lap[3] += iv.w;
     }
     const float4 ccv = W(cc);
@@ -282,7 +297,7 @@ __device__ __forceinline__ void fused2_tile(const Fused2Args& f, const int t) {
       if (inner) laplacian(vq, vlds, crowB, F2_EX4, lapb);
       if (zb == ezb) {
         const float4 iv =
-            inject(a.ent, a.csr_idx, a.csr_w, a.trace_row, eb, eb_end, ezb, inner, slotB);
+            inject(a.ent, a.csr_idx, a.csr_w, a.trace_row, eb, eb_end, ezb, egb, inner, slotB);
         lapb[0] += iv.x; lapb[1] += iv.y; lapb[2] += iv.z; lapb[3] += iv.w;
       }
       w = update(vq[R], q[0], cring[slot(zb)][slotB], bzs[max(zb - za0, 0)], lapb);

@@ -35,8 +35,11 @@ struct InjEntry {
   int csr_beg;  // terms [csr_beg, csr_end)
   int csr_end;
   int grp_end;  // first entry of the next plane group in this tile
-  int pad0, pad1, pad2;
+  int tidx;     // an entry with a single term: its trace index (else -1)
+  float w;      //   and its weight
+  int pad;
 };
+static_assert(sizeof(InjEntry) == 32, "entries are loaded as two 16-byte vectors");
 
 // Storage formats of the wavefield levels (arithmetic is FP32 in all of them).
 enum StoreKind { ST_F32 = 0, ST_F16 = 1, ST_BF16 = 2 };

@@ -211,11 +211,14 @@ __device__ __forceinline__ void step_tile(const StepArgs& a, const int t, const 
 
   // Injection entries of this tile (sorted by plane); ez is the plane of the next
   // group, kept in a register so the per-plane test needs no load.
-  int e = 0, e_end = 0, ez = INT_MAX;
+  int e = 0, e_end = 0, ez = INT_MAX, eg = 0;  // eg: end of the group at plane ez
   if (a.tile_beg != nullptr) {
     e = a.tile_beg[t];
     e_end = a.tile_beg[t + 1];
-    if (e < e_end) ez = a.ent[e].z;
+    if (e < e_end) {
+      ez = a.ent[e].z;
+      eg = a.ent[e].grp_end;
+    }
   }
 
   // Loads that plane zn needs before its own step, kept raw until used: the
@@ -292,20 +295,27 @@ __device__ __forceinline__ void step_tile(const StepArgs& a, const int t, const 
 
     // Fused injection at this plane (uniform branch).
     if (z == ez) {
-      const int ge = a.ent[e].grp_end;
-      for (int i = e + tid; i < ge; i += NTHREADS) {
+      for (int i = e + tid; i < eg; i += NTHREADS) {
         const InjEntry en = a.ent[i];
         float s = 0.f;
-        for (int c = en.csr_beg; c < en.csr_end; ++c)
-          s = fmaf(a.csr_w[c], a.trace_row[a.csr_idx[c]], s);
+        if (en.tidx >= 0) {  // single term, carried in the entry
+          s = fmaf(en.w, a.trace_row[en.tidx], 0.f);
+        } else {
+          for (int c = en.csr_beg; c < en.csr_end; ++c)
+            s = fmaf(a.csr_w[c], a.trace_row[a.csr_idx[c]], s);
+        }
         reinterpret_cast<float*>(inj)[en.local] = s;
       }
       __syncthreads();
       const float4 iv = inj[tid];
       lap[0] += iv.x; lap[1] += iv.y; lap[2] += iv.z; lap[3] += iv.w;
       inj[tid] = zero4;
-      e = ge;
-      ez = e < e_end ? a.ent[e].z : INT_MAX;
+      e = eg;
+      ez = INT_MAX;
+      if (e < e_end) {
+        ez = a.ent[e].z;
+        eg = a.ent[e].grp_end;
+      }
     }
 
     // Damped leapfrog update in increment form:
