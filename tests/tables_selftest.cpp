@@ -1,0 +1,218 @@
+// Host-only self-test of the solver's injection and sampling tables and of its
+// z-chunk policy (paper_1912_00695_amd/csrc/wave_api.cpp, compiled into this test
+// with the host compiler; the kernels' launchers resolve against libwave.so but
+// none is called). For random point sets -- on grid points, off them, repeated,
+// on tile and chunk edges -- the tables are checked against a brute-force
+// reference written here from the definition: every point contributes its
+// trilinear corners (weights (1-t) or t per axis, corners of weight 0 dropped);
+// each distinct grid point becomes one entry of the tile that holds it, entries
+// ordered by (tile, plane, index in the tile), with the contributing (point,
+// weight) terms in point order. Built and run by tests/test_tables_host.py; exits
+// non-zero on failure.
+#include <cmath>
+#include <cstdio>
+#include <cstdlib>
+#include <cstring>
+#include <map>
+#include <random>
+#include <tuple>
+#include <vector>
+
+#include "wave_api.cpp"
+
+using namespace wave;
+
+#define CHECK(c)                                                         \
+  do {                                                                   \
+    if (!(c)) {                                                          \
+      std::fprintf(stderr, "FAILED %s at line %d\n", #c, __LINE__);     \
+      std::exit(1);                                                      \
+    }                                                                    \
+  } while (0)
+
+struct RefTerm {
+  int p;
+  float w;
+};
+using RefKey = std::tuple<int, int, int>;  // tile, plane, index in the tile
+
+static void reference(const wave_grid& g, const Geom& G, const Tiling& T,
+                      const std::vector<double>& xyz, std::map<RefKey, std::vector<RefTerm>>* ent,
+                      std::vector<int>* sidx, std::vector<float>* sw) {
+  const int np = (int)xyz.size() / 3;
+  sidx->assign((size_t)8 * np, 0);
+  sw->assign((size_t)8 * np, 0.f);
+  for (int p = 0; p < np; ++p) {
+    const double f[3] = {xyz[3 * p] / g.hx, xyz[3 * p + 1] / g.hy, xyz[3 * p + 2] / g.hz};
+    int base[3];
+    double t[3];
+    for (int a = 0; a < 3; ++a) {
+      base[a] = (int)std::floor(f[a]);
+      t[a] = f[a] - base[a];
+    }
+    int k = 0;
+    for (int c = 0; c < 8; ++c) {  // x fastest, then y, then z
+      const int d[3] = {c & 1, (c >> 1) & 1, (c >> 2) & 1};
+      double w = 1.0;
+      for (int a = 0; a < 3; ++a) w *= d[a] ? t[a] : 1.0 - t[a];
+      if (w == 0.0) continue;
+      const int i = base[0] + d[0], j = base[1] + d[1], z = base[2] + d[2];
+      (*sidx)[8 * p + k] = (int)((int64_t)z * G.plane + (int64_t)j * G.pitch + i);
+      (*sw)[8 * p + k] = (float)w;
+      ++k;
+      const int tile = ((z / T.zchunk) * T.ntile_y + j / TY) * T.ntile_x + i / TX;
+      (*ent)[RefKey{tile, z, (j % TY) * TX + (i % TX)}].push_back(RefTerm{p, (float)w});
+    }
+  }
+}
+
+static void check_tables(const wave_grid& g, int zchunk, const std::vector<double>& xyz) {
+  const Geom G = make_geom(&g);
+  const Tiling T = make_tiling(G, zchunk, false);
+  const int np = (int)xyz.size() / 3;
+  const Layout L = make_layout(&g, 0, np, WAVE_MODE_FORWARD, 0);
+  const PointTables& P = L.pts[1];
+  Blob B;
+  B.base = L.tables_beg;
+  const size_t size = L.tables_end - L.tables_beg;
+  B.bytes.reset(new char[size]);
+  std::memset(B.bytes.get(), 0xA5, size);  // garbage where nothing is written
+  build_point_tables(&g, G, T, xyz.data(), np, P, B);
+
+  std::map<RefKey, std::vector<RefTerm>> ref;
+  std::vector<int> sidx;
+  std::vector<float> sw;
+  reference(g, G, T, xyz, &ref, &sidx, &sw);
+
+  // sampling corners
+  CHECK(std::memcmp(B.at<int>(P.samp_idx), sidx.data(), sidx.size() * sizeof(int)) == 0);
+  CHECK(std::memcmp(B.at<float>(P.samp_w), sw.data(), sw.size() * sizeof(float)) == 0);
+  // entries, terms, tile ranges, plane groups, single-term fields
+  const int* tb = B.at<int>(P.tile_beg);
+  const InjEntry* ent = B.at<InjEntry>(P.ent);
+  const int* cidx = B.at<int>(P.csr_idx);
+  const float* cw = B.at<float>(P.csr_w);
+  CHECK(tb[0] == 0 && tb[T.nblocks] == (int)ref.size());
+  int e = 0, c = 0;
+  for (const auto& kv : ref) {
+    const int tile = std::get<0>(kv.first);
+    CHECK(tb[tile] <= e && e < tb[tile + 1]);
+    const InjEntry& en = ent[e];
+    CHECK(en.z == std::get<1>(kv.first) && en.local == std::get<2>(kv.first));
+    CHECK(en.csr_beg == c && en.csr_end == c + (int)kv.second.size());
+    for (const RefTerm& t : kv.second) {
+      CHECK(cidx[c] == t.p && cw[c] == t.w);
+      ++c;
+    }
+    if (kv.second.size() == 1) {
+      CHECK(en.tidx == kv.second[0].p && en.w == kv.second[0].w);
+    } else {
+      CHECK(en.tidx == -1);
+    }
+    // the group of en runs to the first entry of the tile on another plane
+    int q = e;
+    while (q < tb[tile + 1] && ent[q].z == en.z) ++q;
+    CHECK(en.grp_end == q);
+    ++e;
+  }
+  for (int t = 0; t < T.nblocks; ++t) CHECK(tb[t] <= tb[t + 1]);
+  // uploaded ranges: every written array, within the table region
+  size_t covered = 0;
+  for (const auto& r : B.used) {
+    CHECK(r.first + r.second <= size);
+    covered += r.second;
+  }
+  const size_t want = ((size_t)T.nblocks + 1) * sizeof(int) + (size_t)e * sizeof(InjEntry) +
+                      (size_t)c * (sizeof(int) + sizeof(float)) +
+                      (size_t)8 * np * (sizeof(int) + sizeof(float));
+  CHECK(covered == want);
+}
+
+static wave_grid grid(int nx, int ny, int nz) {
+  wave_grid g{};
+  g.nx = nx;
+  g.ny = ny;
+  g.nz = nz;
+  g.hx = 10.0;
+  g.hy = 12.0;
+  g.hz = 9.0;
+  g.so = 8;
+  g.dt = 1e-3;
+  g.nt = 10;
+  return g;
+}
+
+static void test_tables() {
+  std::mt19937_64 rng(7);
+  std::uniform_real_distribution<double> U(0.0, 1.0);
+  const int shapes[][3] = {{97, 37, 23}, {160, 48, 70}, {64, 16, 9}, {130, 70, 41}};
+  int cases = 0;
+  for (const auto& s : shapes) {
+    const wave_grid g = grid(s[0], s[1], s[2]);
+    for (int zc : {0, 1, 5, 8}) {
+      for (int kind = 0; kind < 4; ++kind) {
+        std::vector<double> xyz;
+        const int np = kind == 3 ? 1 : 300 + 200 * kind;
+        for (int p = 0; p < np; ++p) {
+          double f[3] = {U(rng) * (g.nx - 1), U(rng) * (g.ny - 1), U(rng) * (g.nz - 1)};
+          if (kind == 0 || (kind == 2 && p % 2 == 0))
+            for (double& v : f) v = std::floor(v);  // on grid points
+          if (kind == 1 && p % 5 == 0) {           // on tile and chunk edges
+            f[0] = std::min<double>(g.nx - 1, 63 + (p % 3) * 0.5);
+            f[1] = std::min<double>(g.ny - 1, 15 + (p % 2) * 0.25);
+          }
+          if (kind == 2 && p % 7 == 0 && p > 0)    // repeats of the previous point
+            for (int a = 0; a < 3; ++a)
+              f[a] = xyz[3 * (p - 1) + a] / (a == 0 ? g.hx : a == 1 ? g.hy : g.hz);
+          xyz.push_back(f[0] * g.hx);
+          xyz.push_back(f[1] * g.hy);
+          xyz.push_back(f[2] * g.hz);
+        }
+        check_tables(g, zc, xyz);
+        ++cases;
+      }
+    }
+    // a full plane of receivers in raster order (the presorted path)
+    std::vector<double> plane;
+    for (int j = 0; j < g.ny; ++j)
+      for (int i = 0; i < g.nx; ++i) {
+        plane.push_back(i * g.hx);
+        plane.push_back(j * g.hy);
+        plane.push_back(5 * g.hz);
+      }
+    check_tables(g, 0, plane);
+    ++cases;
+  }
+  // no points
+  check_tables(grid(97, 37, 23), 0, {});
+  std::printf("tables: %d cases\n", cases + 1);
+}
+
+static void test_tiling() {
+  const auto zc = [](int n, bool naive16) {
+    wave_grid g = grid(n, n, n);
+    return make_tiling(make_geom(&g), 0, naive16);
+  };
+  // about 512 workgroups of one long chunk each
+  CHECK(zc(256, false).zchunk == 32 && zc(256, false).nblocks == 512);
+  CHECK(zc(320, false).zchunk == 64 && zc(320, false).nblocks == 500);
+  CHECK(zc(384, false).zchunk == 128 && zc(384, false).nblocks == 432);
+  CHECK(zc(512, false).zchunk == 256 && zc(512, false).nblocks == 512);
+  CHECK(zc(64, false).zchunk == 8);  // at least 8 planes
+  // naive 16-bit storage: chunks of at most 32 planes, ~20 for large grids
+  CHECK(zc(256, true).zchunk == 32);
+  CHECK(zc(512, true).zchunk == 20);
+  for (int n : {40, 97, 200, 333, 700}) {
+    const Tiling T = zc(n, false);
+    CHECK(T.zchunk >= 1 && T.zchunk <= MAXZCHUNK && T.zchunk <= n);
+    CHECK(T.nchunk * T.zchunk >= n && (T.nchunk - 1) * T.zchunk < n);
+  }
+  std::printf("tiling: OK\n");
+}
+
+int main() {
+  test_tables();
+  test_tiling();
+  std::printf("OK\n");
+  return 0;
+}
