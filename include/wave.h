@@ -222,7 +222,11 @@ typedef struct {
 } wave_stats;
 
 /* Create an engine with a device pool of hbm_budget_bytes (allocated here, on the
- * current device) and at most max_slots resident shots. */
+ * current device) and at most max_slots resident shots. Resident shots advance in
+ * groups of one space order whose per-step arrays fit the Infinity Cache together
+ * (224 MB; WAVE_ENGINE_GROUP_MB overrides, read when the set of shots changes),
+ * several steps of a group back to back; a shot's results do not depend on the
+ * grouping or on the other shots. */
 int wave_engine_create(size_t hbm_budget_bytes, int max_slots, void** engine);
 /* Queue a request; its inputs are copied. WAVE_EBUSY if it can never fit the
  * budget; validation errors as for wave_forward. *id identifies it. */

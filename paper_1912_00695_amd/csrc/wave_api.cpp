@@ -322,11 +322,12 @@ bool fused_tiling_ok(const Ctx& C) { return C.L.fused && C.T.zchunk >= C.g->so; 
 
 // Whether an FP32 forward solve without checkpoints takes the two-step kernel, and
 // its z-chunk length. Measured on MI355X (64-plane chunks, cubic grids, two-step vs
-// one-step): SO2 -5 % at 256^3, +12 % at 320^3, +37 % at 512^3; SO4 -8 % at 256^3,
-// -2 % at 384^3, +9 % at 416^3, +24 % at 512^3; SO6 -2 % at 416^3, +9 % at 448^3,
-// +12 % at 512^3; SO8 (158 registers per lane, one 512-thread workgroup per CU) -6 %
+// the one-step kernel with its default tiling): SO2 +2 % at 320^3, +0 % at 384^3,
+// +22 % at 448^3, +34 % at 512^3; SO4 -15 % at 256^3, -4 % at 320^3, -6 % at 384^3,
+// +14 % at 448^3, +23 % at 512^3; SO6 -11 % at 320^3, -14 % at 384^3, +6 % at 448^3,
+// +11 % at 512^3; SO8 (158 registers per lane, one 512-thread workgroup per CU) -10 %
 // at 512^3. Below these sizes the one-step kernel's working set is largely served by
-// the 256 MiB Infinity Cache. Auto: radius r <= 3 and at least kFusedMinPoints[r]
+// the 256 MiB Infinity Cache; longer two-step chunks (128, 256 planes) lost at SO2/SO4. Auto: radius r <= 3 and at least kFusedMinPoints[r]
 // grid points. WAVE_FUSED=1 forces it (radius <= 4; z-chunks of the one-step policy
 // unless WAVE_F2_ZCHUNK is set), 0 disables it.
 constexpr int64_t kFusedMinPoints[4] = {0, 30000000, 60000000, 80000000};
