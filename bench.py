@@ -346,10 +346,29 @@ def cpu_baseline(P, target_s=20.0):
                 break
     except OSError:
         pass
-    return {"value": npts * nsteps / el / 1e9, "unit": "Gpt-updates/s",
-            "cores": oracle.num_threads(), "kind": "oracle", "cpu_model": cpu,
-            "sample": "FP64 oracle, 256^3 SO8 two-layer + 40-cell sponge, source and 256 "
-                      "receivers, first %d of the 500 time steps (%.1f s)" % (nsteps, el)}
+    res = {"value": npts * nsteps / el / 1e9, "unit": "Gpt-updates/s",
+           "cores": oracle.num_threads(), "kind": "oracle", "cpu_model": cpu,
+           "sample": "FP64 oracle, 256^3 SO8 two-layer + 40-cell sponge, source and 256 "
+                     "receivers, first %d of the 500 time steps (%.1f s)" % (nsteps, el)}
+    # one thread on the small plain case: 64^3 SO4, homogeneous 1500 m/s, Gaussian
+    # pulse at rest at the centre, 100 steps
+    from paper_1912_00695_amd import inputs
+    n1, h1 = (64, 64, 64), (10.0, 10.0, 10.0)
+    v1 = inputs.constant(n1, 1500.0)
+    g1 = oracle.Grid(n1, h1, 4, 0.5 * oracle.cfl_dt_max(4, 1500.0, h1), 100, vmax=1500.0)
+    u0 = inputs.gaussian_pulse(n1, (32, 32, 32), 3.0)
+    um1 = oracle.taylor_start(g1, v1, u0)
+    nthreads = oracle.num_threads()
+    oracle.set_num_threads(1)
+    try:
+        t0 = time.perf_counter()
+        oracle.forward(g1, v1, None, None, None, u0=u0, um1=um1)
+        el1 = time.perf_counter() - t0
+    finally:
+        oracle.set_num_threads(nthreads)
+    res["single_thread_64cube_so4"] = {"value": 64 ** 3 * 100 / el1 / 1e9,
+                                       "unit": "Gpt-updates/s", "seconds": round(el1, 2)}
+    return res
 
 
 def main():

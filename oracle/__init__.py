@@ -66,6 +66,8 @@ def lib():
         L.oracle_gradient_image.restype = ctypes.c_int
         L.oracle_num_threads.argtypes = []
         L.oracle_num_threads.restype = ctypes.c_int
+        L.oracle_set_num_threads.argtypes = [ctypes.c_int]
+        L.oracle_set_num_threads.restype = None
         _lib = L
     return _lib
 
@@ -249,3 +251,9 @@ def rtm_image(grid, vel, wavelet, src_xyz, rec_xyz, rec_data, ckpt_every=0):
 
 def num_threads():
     return lib().oracle_num_threads()
+
+
+def set_num_threads(n):
+    """Threads of the following oracle calls (timing only; results do not depend on
+    it: every loop writes disjoint points)."""
+    lib().oracle_set_num_threads(int(n))

@@ -397,10 +397,13 @@ int oracle_gradient(const ogrid *g, const double *vel, const double *wavelet,
                                ckpt_every, grad_m, grad_vel, grad_wavelet, NULL);
 }
 
-/* Number of threads OpenMP would use (for reporting).                        */
+/* Number of threads OpenMP would use (for reporting), and a way to change it
+ * (a single-thread timing beside the all-core one).                         */
 #ifdef _OPENMP
 #include <omp.h>
 int oracle_num_threads(void) { return omp_get_max_threads(); }
+void oracle_set_num_threads(int n) { omp_set_num_threads(n > 0 ? n : 1); }
 #else
 int oracle_num_threads(void) { return 1; }
+void oracle_set_num_threads(int n) { (void)n; }
 #endif
