@@ -192,7 +192,7 @@ def _with_nt(case, nt):
     return c
 
 
-@pytest.mark.parametrize("so", [4, 8, 16])
+@pytest.mark.parametrize("so", [2, 4, 6, 8, 10, 12, 14, 16, 24])
 def test_chunk_lengths_give_identical_results(so):
     """z-chunks of 1, 2, 5 and 23 planes (the whole grid) against the default
     chunking (8 planes on this 97 x 37 x 23 grid): every point's update reads the
