@@ -8,6 +8,7 @@
 #include <cstdlib>
 #include <cstring>
 #include <map>
+#include <mutex>
 #include <vector>
 
 #include "../../include/wave.h"
@@ -437,12 +438,70 @@ void sponge_1d(int n, int lo, int hi, double h, double vmax, double dt, float* b
   for (int i = 0; i < n; ++i) b[i] = (float)(0.5 * dt * gam[i]);
 }
 
+// Page-locked staging buffers for the table uploads, reused across calls: a buffer
+// is taken for one call's tables and returned when that call's Blob is deleted,
+// which for a solve happens in the stream's host callback after the upload has run
+// (no HIP call is made there). The pool only grows, to at most the number of
+// calls in flight at once, and lives until the process ends.
+class StagingPool {
+ public:
+  char* take(size_t n) {
+    std::lock_guard<std::mutex> lk(mu_);
+    Buf* best = nullptr;
+    for (Buf& b : bufs_)
+      if (!b.busy && b.n >= n && (best == nullptr || b.n < best->n)) best = &b;
+    if (best != nullptr) {
+      best->busy = true;
+      return best->p;
+    }
+    size_t sz = (size_t)1 << 20;
+    while (sz < n) sz <<= 1;
+    void* p = nullptr;
+    if (hipHostMalloc(&p, sz, hipHostMallocDefault) != hipSuccess || p == nullptr) return nullptr;
+    bufs_.push_back(Buf{static_cast<char*>(p), sz, true});
+    return static_cast<char*>(p);
+  }
+  void give(char* p) {
+    std::lock_guard<std::mutex> lk(mu_);
+    for (Buf& b : bufs_)
+      if (b.p == p) b.busy = false;
+  }
+
+ private:
+  struct Buf {
+    char* p;
+    size_t n;
+    bool busy;
+  };
+  std::mutex mu_;
+  std::vector<Buf> bufs_;
+};
+
+StagingPool& staging() {
+  static StagingPool* pool = new StagingPool;  // never destroyed: callbacks may run late
+  return *pool;
+}
+
+void Blob::alloc(size_t n) {
+  bytes = staging().take(n);
+  pinned = bytes != nullptr;
+  if (!pinned) bytes = new char[n];
+}
+
+Blob::~Blob() {
+  if (bytes == nullptr) return;
+  if (pinned)
+    staging().give(bytes);
+  else
+    delete[] bytes;
+}
+
 void delete_blob(void* p) { delete static_cast<Blob*>(p); }
 
 hipError_t upload_blob(const Blob& b, char* dst, hipStream_t s) {
   for (const auto& r : b.used) {
     const hipError_t e =
-        hipMemcpyAsync(dst + r.first, b.bytes.get() + r.first, r.second, hipMemcpyHostToDevice, s);
+        hipMemcpyAsync(dst + r.first, b.bytes + r.first, r.second, hipMemcpyHostToDevice, s);
     if (e != hipSuccess) return e;
   }
   return hipSuccess;
@@ -490,7 +549,7 @@ Blob* build_blob(const Ctx& C, const double* src, int nsrc, const double* rec, i
   const wave_grid* g = C.g;
   Blob* B = new Blob;
   B->base = C.L.tables_beg;
-  B->bytes.reset(new char[C.L.tables_end - C.L.tables_beg]);
+  B->alloc(C.L.tables_end - C.L.tables_beg);
   float* bx = B->at<float>(C.L.bx);
   sponge_1d(g->nx, g->nbl[0], g->nbl[1], g->hx, g->vmax, g->dt, bx);
   std::fill(bx + g->nx, bx + C.G.pitch, 0.f);  // padding columns

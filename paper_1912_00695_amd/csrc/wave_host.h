@@ -37,15 +37,25 @@ struct Layout {
   size_t total;
 };
 
-// Host image of the table region. Allocated uninitialised (the point tables are
-// sized for 8 corners per point, most of it unused for on-grid points); the
-// builders record the ranges they write, and only those are uploaded.
+// Host image of the table region, in page-locked memory from a process-wide pool of
+// staging buffers (plain heap memory if that allocation fails), so that its upload
+// is an asynchronous copy; the buffer returns to the pool when the Blob is deleted
+// (after the upload, from the stream's host callback). Uninitialised (the point
+// tables are sized for 8 corners per point, most of it unused for on-grid points):
+// the builders record the ranges they write, and only those are uploaded.
 struct Blob {
-  std::unique_ptr<char[]> bytes;
+  char* bytes = nullptr;
+  bool pinned = false;
   size_t base = 0;
   std::vector<std::pair<size_t, size_t>> used;  // (offset from base, bytes)
+  Blob() = default;
+  Blob(const Blob&) = delete;
+  Blob& operator=(const Blob&) = delete;
+  ~Blob();
+  // take n bytes of storage (pinned when possible)
+  void alloc(size_t n);
   template <class T>
-  T* at(size_t off) { return reinterpret_cast<T*>(bytes.get() + (off - base)); }
+  T* at(size_t off) { return reinterpret_cast<T*>(bytes + (off - base)); }
   void mark(size_t off, size_t n) {
     if (n > 0) used.push_back({off - base, n});
   }

@@ -75,8 +75,8 @@ static void check_tables(const wave_grid& g, int zchunk, const std::vector<doubl
   Blob B;
   B.base = L.tables_beg;
   const size_t size = L.tables_end - L.tables_beg;
-  B.bytes.reset(new char[size]);
-  std::memset(B.bytes.get(), 0xA5, size);  // garbage where nothing is written
+  B.bytes = new char[size];  // heap storage (the destructor frees it)
+  std::memset(B.bytes, 0xA5, size);  // garbage where nothing is written
   build_point_tables(&g, G, T, xyz.data(), np, P, B);
 
   std::map<RefKey, std::vector<RefTerm>> ref;
