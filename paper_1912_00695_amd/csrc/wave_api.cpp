@@ -231,8 +231,7 @@ void build_point_tables(const wave_grid* g, const Geom& G, const Tiling& T, cons
   // by tile, then a stable sort of each tile's terms by plane and local index
   // (skipped where they are in that order already, as for points given in raster
   // order on a grid plane), puts the terms of one grid point together in point
-  // order, the order in which the kernels sum them. 65,536 receivers: 7 ms on a
-  // grid plane, 33 ms off the grid, where a map keyed by grid point took 35-90 ms.
+  // order, the order in which the kernels sum them.
   struct Term {
     int tile, z, local, p;
     float w;
@@ -269,9 +268,30 @@ void build_point_tables(const wave_grid* g, const Geom& G, const Tiling& T, cons
   const auto by_plane = [](const Term& a, const Term& b) {
     return a.z != b.z ? a.z < b.z : a.local < b.local;
   };
+  // A tile whose terms span a few planes (points off a grid plane touch two) is
+  // ordered by a stable counting sort on (plane, index in the tile) in cache; wider
+  // spans by a stable comparison sort.
+  std::vector<Term> tmp;
+  std::vector<int> pos;
   for (int t = 0; t < ntiles; ++t) {
     const auto b0 = sorted.begin() + cnt[t], b1 = sorted.begin() + cnt[(size_t)t + 1];
-    if (b1 - b0 > 1 && !std::is_sorted(b0, b1, by_plane)) std::stable_sort(b0, b1, by_plane);
+    if (b1 - b0 <= 1 || std::is_sorted(b0, b1, by_plane)) continue;
+    int zlo = b0->z, zhi = b0->z;
+    for (auto it = b0; it != b1; ++it) {
+      zlo = std::min(zlo, it->z);
+      zhi = std::max(zhi, it->z);
+    }
+    if (zhi - zlo >= 4) {
+      std::stable_sort(b0, b1, by_plane);
+      continue;
+    }
+    const int nkey = (zhi - zlo + 1) * TX * TY;
+    pos.assign((size_t)nkey + 1, 0);
+    for (auto it = b0; it != b1; ++it) ++pos[(size_t)(it->z - zlo) * TX * TY + it->local + 1];
+    for (int k = 0; k < nkey; ++k) pos[(size_t)k + 1] += pos[k];
+    tmp.resize(b1 - b0);
+    for (auto it = b0; it != b1; ++it) tmp[pos[(size_t)(it->z - zlo) * TX * TY + it->local]++] = *it;
+    std::copy(tmp.begin(), tmp.end(), b0);
   }
   // one entry per distinct (tile, plane, local index), its terms in CSR order
   InjEntry* ent = B.at<InjEntry>(P.ent);

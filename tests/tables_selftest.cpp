@@ -181,6 +181,19 @@ static void test_tables() {
         plane.push_back(5 * g.hz);
       }
     check_tables(g, 0, plane);
+    // the same plane off the grid points (two planes of corners per tile: the
+    // counting-sort path), and shifted across a chunk boundary
+    for (const double zf : {5.3, 7.5}) {
+      std::vector<double> off;
+      for (int j = 0; j + 1 < g.ny; ++j)
+        for (int i = 0; i + 1 < g.nx; ++i) {
+          off.push_back((i + 0.37) * g.hx);
+          off.push_back((j + 0.61) * g.hy);
+          off.push_back(zf * g.hz);
+        }
+      check_tables(g, 8, off);
+      cases += 1;
+    }
     ++cases;
   }
   // no points
