@@ -32,7 +32,12 @@
  *  - Pointers named *_h are host memory, read only during the call. All other
  *    array pointers are device memory owned by the caller.
  *  - The caller owns the workspace (device, 256-byte aligned, at least
- *    wave_workspace_bytes()). Solver calls allocate no device memory.
+ *    wave_workspace_bytes()). Solver calls allocate no device memory. Each call
+ *    builds its source/receiver tables on the host in a page-locked staging
+ *    buffer taken from a process-wide pool (hipHostMalloc on first need, kept
+ *    for the life of the process, about 12 B per grid point of a point's eight
+ *    trilinear corners plus 4 B per tile) and uploads them asynchronously on
+ *    `hip_stream`; the buffer returns to the pool when the upload has run.
  *  - Work is enqueued on `hip_stream` (a hipStream_t, NULL = the default
  *    stream) and the call returns; outputs are valid after that stream
  *    synchronises. Calls on distinct (workspace, stream) pairs may run
