@@ -35,9 +35,10 @@
  *    wave_workspace_bytes()). Solver calls allocate no device memory. Each call
  *    builds its source/receiver tables on the host in a page-locked staging
  *    buffer taken from a process-wide pool (hipHostMalloc on first need, kept
- *    for the life of the process, about 12 B per grid point of a point's eight
- *    trilinear corners plus 4 B per tile) and uploads them asynchronously on
- *    `hip_stream`; the buffer returns to the pool when the upload has run.
+ *    for the life of the process; sized like the workspace's table region, at
+ *    most 384 B per source or receiver point plus 4 B per 64x16 tile and plane)
+ *    and uploads them asynchronously on `hip_stream`; the buffer returns to the
+ *    pool when the upload has run.
  *  - Work is enqueued on `hip_stream` (a hipStream_t, NULL = the default
  *    stream) and the call returns; outputs are valid after that stream
  *    synchronises. Calls on distinct (workspace, stream) pairs may run
