@@ -218,3 +218,41 @@ def test_chunk_lengths_give_identical_results(so):
               flush=True)
         assert np.array_equal(g["u_final"], ref["u_final"])
         assert np.array_equal(g["rec"], ref["rec"])
+
+
+def test_concurrent_calls_on_two_streams():
+    """Two different solves, each with its own workspace, enqueued alternately three
+    times on two streams: every result is bitwise that of the same solve run alone
+    (concurrent calls share only the library's pool of host staging buffers for
+    their tables; the second case's 3,000 extra off-grid receivers make its tables
+    large)."""
+    import torch
+    from paper_1912_00695_amd import inputs, wave
+    dev = torch.device("cuda:0")
+    cases = [ragged_case(8, nt=40, seed=80), ragged_case(4, nt=40, seed=81)]
+    c1 = cases[1]
+    c1.rec = np.concatenate([c1.rec, inputs.random_points(c1.n, c1.h, 3000, 82)])
+    for c in cases:
+        _oracle_inputs(c)
+    alone = [_run(c) for c in cases]
+    t = lambda a: None if a is None else torch.from_numpy(
+        np.ascontiguousarray(a, dtype=np.float32)).to(dev)
+    dev_in = [(t(c.vel), t(c.wavelet), t(c.u0), t(c.um1)) for c in cases]
+    streams = [torch.cuda.Stream(device=dev), torch.cuda.Stream(device=dev)]
+    wss, outs = [], []
+    for c, s in zip(cases, streams):
+        with torch.cuda.stream(s):
+            wss.append(torch.empty(wave.workspace_bytes(c.wgrid(), len(c.src), len(c.rec)),
+                                   dtype=torch.uint8, device=dev))
+    torch.cuda.synchronize()
+    print("two streams, 3 rounds", flush=True)
+    for _ in range(3):
+        for k, (c, s) in enumerate(zip(cases, streams)):
+            vel, wav, u0, um1 = dev_in[k]
+            with torch.cuda.stream(s):
+                outs.append((k, wave.forward(c.wgrid(), vel, wav, c.src, c.rec, u0=u0, um1=um1,
+                                             want_final=True, workspace=wss[k], stream=s)))
+    torch.cuda.synchronize()
+    for k, o in outs:
+        assert np.array_equal(o["rec"].cpu().numpy(), alone[k]["rec"])
+        assert np.array_equal(o["u_final"].cpu().numpy(), alone[k]["u_final"])
