@@ -36,9 +36,14 @@ namespace wave {
 #define WAVE_PF2_MASK 0x0
 #endif
 // bit R of WAVE_HRING_MASK: load the xy-halo of each plane R planes ahead (with the
-// queue head of the same plane) and park it in LDS until the plane is staged
+// queue head of the same plane) and park it in LDS until the plane is staged; by
+// default only in launches without non-temporal streams (WAVE_HRING_NT=1: in those
+// too)
 #ifndef WAVE_HRING_MASK
 #define WAVE_HRING_MASK 0x1FE  // radius 1..8
+#endif
+#ifndef WAVE_HRING_NT
+#define WAVE_HRING_NT 0
 #endif
 constexpr bool zunroll2(int r) { return ((WAVE_ZUNROLL_MASK) >> r) & 1; }
 constexpr bool prefetch2(int r) { return ((WAVE_PF2_MASK) >> r) & 1; }
@@ -71,9 +76,6 @@ __device__ __forceinline__ void step_tile(const StepArgs& a, const int t, const 
   // of a step is resident at once. With non-temporal streams (grids whose step
   // does not fit the Infinity Cache, swept in several rounds of workgroups) it
   // ranged from +1 % to -8 % and is off.
-#ifndef WAVE_HRING_NT
-#define WAVE_HRING_NT 0
-#endif
   constexpr bool HRG = halo_ring(R) && (!NT || WAVE_HRING_NT);
   using Raw = typename Store<ST>::Raw;
   __shared__ Raw hbuf[HRG ? R + 1 : 1][HRG ? NH : 1];
