@@ -413,19 +413,9 @@ def main():
     el, wall = time_solves(solver, args.steps, args.warmup, per_solve)
     npts = args.n ** 3
     gpts = npts * P["nt"] * args.steps / el / 1e9
-    whole_s = el / (args.steps * P["nt"])  # per step, set-up of each solve included
-    # The step kernel's average launch duration: the slope of the event-timed solve
-    # time between nt and nt/2 steps of the same workload, so that each solve's
-    # fixed work (tables, v^2 dt^2, initial levels, the last sampling launch) drops out.
-    launch_s = whole_s
-    if P["nt"] >= 4:
-        half = Solver(c2_problem(args.so, nt=P["nt"] // 2, n=(args.n,) * 3), dev)
-        el_half, _ = time_solves(half, args.steps, args.warmup)
-        del half
-        launch_s = (el - el_half) / (args.steps * (P["nt"] - P["nt"] // 2))
+    launch_s = el / (args.steps * P["nt"])
     achieved = ALG_BYTES_PER_PT * npts / launch_s / 1e9
-    log("Gpt/s %.2f  per-step %.2f us  effective %.0f GB/s  (whole solve: %.2f us per step)" %
-        (gpts, launch_s * 1e6, achieved, whole_s * 1e6))
+    log("Gpt/s %.2f  per-step %.2f us  effective %.0f GB/s" % (gpts, launch_s * 1e6, achieved))
     out = {
         "metric": METRIC, "value": round(gpts, 3), "unit": "Gpt-updates/s",
         "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
@@ -442,8 +432,6 @@ def main():
                      "kernel": "step_kernel<%d,false>" % (args.so // 2),
                      "alg_bytes_per_launch": ALG_BYTES_PER_PT * npts,
                      "avg_launch_us": round(launch_s * 1e6, 3),
-                     "avg_launch_method": "slope of event-timed solves of nt and nt/2 steps",
-                     "per_step_us_whole_solve": round(whole_s * 1e6, 3),
                      "kernel_source_hash": kernel_hash()},
         "wall_s_timed": round(wall, 4),
         "per_solve": {"median_gpts": round(npts * P["nt"] / sorted(per_solve)[len(per_solve) // 2]
