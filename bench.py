@@ -56,7 +56,7 @@ def measured_traffic():
     return float(t.group(1))
 
 
-def c2_problem(so, nt=500, n=(256, 256, 256)):
+def c2_problem(so, nt=500, n=(256, 256, 256), path=0, zchunk=0):
     import numpy as np
     from paper_1912_00695_amd import inputs, wave
     h = (10.0, 10.0, 10.0)
@@ -66,7 +66,7 @@ def c2_problem(so, nt=500, n=(256, 256, 256)):
     src = inputs.point((n[0] // 2, n[1] // 2, n[2] // 2), h)
     rec = inputs.line_x(n, h, n[1] // 2, 20)
     wav = inputs.ricker(10.0, dt, nt)[:, None]
-    grid = wave.make_grid(n, h, so, dt, nt, (40,) * 6, vmax=vmax)
+    grid = wave.make_grid(n, h, so, dt, nt, (40,) * 6, vmax=vmax, path=path, zchunk=zchunk)
     return dict(grid=grid, vel=vel, src=src, rec=rec, wav=wav, n=n, nt=nt, so=so, dt=dt,
                 h=h, vmax=vmax, nbl=(40,) * 6, np=np)
 
@@ -74,7 +74,7 @@ def c2_problem(so, nt=500, n=(256, 256, 256)):
 class Solver:
     """Device-resident inputs and a reusable workspace for repeated solves."""
 
-    def __init__(self, P, dev):
+    def __init__(self, P, dev, unfactorised=False):
         import torch
         from paper_1912_00695_amd import wave
         self.P, self.wave, self.torch = P, wave, torch
@@ -83,10 +83,12 @@ class Solver:
         self.rec_out = torch.empty((P["nt"], len(P["rec"])), dtype=torch.float32, device=dev)
         nbytes = wave.workspace_bytes(P["grid"], len(P["src"]), len(P["rec"]))
         self.ws = torch.empty(nbytes, dtype=torch.uint8, device=dev)
+        self.unfactorised = unfactorised
 
     def run(self):
         self.wave.forward(self.P["grid"], self.vel, self.wav, self.P["src"], self.P["rec"],
-                          workspace=self.ws, rec_out=self.rec_out)
+                          workspace=self.ws, rec_out=self.rec_out,
+                          unfactorised=self.unfactorised)
 
 
 def time_solves(solver, steps, warmup, per_solve=None):
@@ -162,19 +164,17 @@ def two_step_leg(dev):
     """Temporal blocking: the forward solve with two fused leapfrog steps per launch
     (64-plane z-chunks) against one step per launch, on the sweep's 256^3 workload and
     at 512^3 (FP32; 20 algorithmic bytes per point per two-step launch)."""
+    from paper_1912_00695_amd import wave
     res = {}
     for n, so, nt in ((256, 4, 500), (256, 8, 500), (512, 2, 100), (512, 4, 100), (512, 6, 100),
                       (512, 8, 100)):
         item = {}
-        for name, flag in (("two_step", "1"), ("one_step", "0")):
-            os.environ["WAVE_FUSED"] = flag
-            os.environ["WAVE_F2_ZCHUNK"] = "64"
-            S = Solver(c2_problem(so, nt=nt, n=(n, n, n)), dev)
+        for name, path, zc in (("two_step", wave.PATH_TWO_STEP, 64),
+                               ("one_step", wave.PATH_ONE_STEP, 0)):
+            S = Solver(c2_problem(so, nt=nt, n=(n, n, n), path=path, zchunk=zc), dev)
             e, _ = time_solves(S, 2, 1)
             item[name + "_gpts"] = round(n ** 3 * nt * 2 / e / 1e9, 2)
             del S
-        os.environ.pop("WAVE_FUSED", None)
-        os.environ.pop("WAVE_F2_ZCHUNK", None)
         item["speedup"] = round(item["two_step_gpts"] / item["one_step_gpts"], 3)
         res["%d^3_so%d" % (n, so)] = item
         log("two-step %d^3 SO%d: %s" % (n, so, item))
@@ -196,17 +196,15 @@ def basic_leg(dev):
     for so in (8, 12, 16, 24):
         item = {}
         fields = {}
-        for name, flag in (("basic", "1"), ("factorised", "0")):
-            os.environ["WAVE_BASIC"] = flag
+        for name, basic in (("basic", True), ("factorised", False)):
             P = c2_problem(so)
-            S = Solver(P, dev)
+            S = Solver(P, dev, unfactorised=basic)
             e, _ = time_solves(S, 2, 1)
             item[name + "_gpts"] = round(256 ** 3 * 500 * 2 / e / 1e9, 2)
             out = wave.forward(P["grid"], S.vel, S.wav, P["src"], P["rec"], want_final=True,
-                               workspace=S.ws)
+                               workspace=S.ws, unfactorised=basic)
             fields[name] = out["u_final"].double()
             del S, out
-        os.environ.pop("WAVE_BASIC", None)
         item["speedup_factorised_over_basic"] = round(item["factorised_gpts"] / item["basic_gpts"], 3)
         item["basic_field_rel_l2_vs_factorised"] = float(
             torch.linalg.norm(fields["basic"] - fields["factorised"]) /

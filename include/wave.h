@@ -65,6 +65,7 @@ extern "C" {
 #define WAVE_EDEVICE (-4) /* a HIP runtime call failed                                      */
 #define WAVE_EBUSY (-5)   /* serving engine: request exceeds the memory budget              */
 #define WAVE_EAGAIN (-6)  /* serving engine: result not ready yet                           */
+#define WAVE_ELIMIT (-7)  /* problem larger than the static scratch of wave_forward_noalloc */
 
 /* Wavefield storage formats (arithmetic is FP32 in every format). The 16-bit
  * formats store each level as value * 2^e with a power-of-two scale e chosen per
@@ -76,6 +77,22 @@ extern "C" {
 #define WAVE_STORE_F16 1
 #define WAVE_STORE_BF16 2
 #define WAVE_STORE_DIFF 16
+/* WAVE_STORE_BF16 without WAVE_STORE_DIFF is diagnostic only: BF16 keeps 8 bits of
+ * mantissa and storing two rounded levels turns each rounding into a velocity error,
+ * so over long runs the error exceeds the signal (measured rel-L2 above 1 against
+ * the FP64 oracle after 1000 steps of a 160^3 SO8 case). It is accepted so that
+ * its error can be measured and stated. */
+
+/* Execution-path flags (wave_grid.path). They choose kernels, launch shapes and
+ * cache hints, never the arithmetic: every path evaluates each point's update with
+ * the same expression (one-step and two-step kernels agree to FP32 contraction
+ * differences, every other choice is bitwise neutral). 0 lets the library choose. */
+#define WAVE_PATH_ONE_STEP 1  /* never the two-step kernel                            */
+#define WAVE_PATH_TWO_STEP 2  /* the two-step kernel wherever it applies (FP32 storage,
+                                 SO <= 8, no checkpoints, z-chunks of >= SO planes)    */
+#define WAVE_PATH_STREAM 4    /* non-temporal hints on the streamed arrays             */
+#define WAVE_PATH_CACHED 8    /* no non-temporal hints                                 */
+#define WAVE_PATH_LINEAR 16   /* workgroups in plain tile order (no XCD-aware order)   */
 
 /* Workspace modes for wave_workspace_bytes(). */
 #define WAVE_MODE_FORWARD 0
@@ -95,6 +112,11 @@ typedef struct {
                           promise; sets the sponge strength and the dt check         */
   int32_t storage;     /* WAVE_STORE_F32 | WAVE_STORE_F16 | WAVE_STORE_BF16, the last two
                           optionally | WAVE_STORE_DIFF                               */
+  int32_t path;        /* WAVE_PATH_* flags (0 = chosen by the library); ONE_STEP with
+                          TWO_STEP, STREAM with CACHED, or unknown bits: WAVE_EINVAL */
+  int32_t zchunk;      /* planes per z-chunk of the stencil sweep, 1..256 (0 = chosen
+                          by the library: about 512 workgroups; 64 planes for the
+                          two-step kernel); results do not depend on it              */
 } wave_grid;
 
 /* Largest stable dt of the leapfrog scheme (von Neumann):
@@ -133,17 +155,29 @@ size_t wave_checkpoint_bytes(const wave_grid* g, int ckpt_every);
  * large grids (SO2 from 3e7, SO4 from 6e7, SO6 from 8e7 points), two fused steps
  * per launch (temporal blocking); both evaluate every point's update with the same
  * expression. For FP32 storage at SO <= 8 the forward workspace holds two extra
- * levels for that kernel. Environment (tuning and ablation, read at every call):
- * WAVE_FUSED=0/1 disables/forces the two-step kernel (SO <= 8); WAVE_BASIC=1 runs
- * the unfactorised update of the paper's SO2 listing (SO 8, 12, 16, 24 only, else
- * WAVE_EINVAL); WAVE_ZCHUNK, WAVE_F2_ZCHUNK, WAVE_NT, WAVE_XCD_REMAP override the
- * z-chunk length, non-temporal streams and block order.
+ * levels for that kernel. g->path and g->zchunk select among the paths; nothing
+ * else (no environment variable) does.
  * Returns WAVE_OK or a negative status. */
 int wave_forward(const wave_grid* g, const float* vel, const float* wavelet,
                  const double* src_xyz_h, int nsrc, const double* rec_xyz_h, int nrec,
                  float* rec_out, const float* u0, const float* um1, float* u_final,
                  float* ckpt, int ckpt_every, void* workspace, size_t ws_bytes,
                  void* hip_stream);
+
+/* Ablation of the paper's basic-versus-aggressive experiment (Section 4, Tables 2
+ * and 3): the forward solve of wave_forward with the update evaluated in the
+ * unfactorised form of the paper's SO2 listing (Section 2.1), generalised to the
+ * star stencil of order SO: every term with its own coefficient and its own
+ * division by r0 = dt m + dt^2 damp / 2, m = 1/v^2, damp = m gamma. Same
+ * mathematics as wave_forward, more FP32 roundings and one division per term.
+ * FP32 storage, SO 8, 12, 16 or 24, no checkpoints (else WAVE_EINVAL); one launch
+ * per step; workspace as for wave_forward (WAVE_MODE_FORWARD). Arguments as for
+ * wave_forward. */
+int wave_forward_unfactorised(const wave_grid* g, const float* vel, const float* wavelet,
+                              const double* src_xyz_h, int nsrc, const double* rec_xyz_h,
+                              int nrec, float* rec_out, const float* u0, const float* um1,
+                              float* u_final, void* workspace, size_t ws_bytes,
+                              void* hip_stream);
 
 /* Backward propagation: the exact transpose of wave_forward's map from
  * wavelet to receiver data (zero initial state). Runs
@@ -230,10 +264,14 @@ typedef struct {
 /* Create an engine with a device pool of hbm_budget_bytes (allocated here, on the
  * current device) and at most max_slots resident shots. Resident shots advance in
  * groups of one space order whose per-step arrays fit the Infinity Cache together
- * (224 MB; WAVE_ENGINE_GROUP_MB overrides, read when the set of shots changes),
- * several steps of a group back to back; a shot's results do not depend on the
- * grouping or on the other shots. */
+ * (224 MB unless wave_engine_set_group_bytes says otherwise), several steps of a
+ * group back to back; a shot's results do not depend on the grouping or on the
+ * other shots. A request's zchunk (0: 32 planes) sets its tiling in the engine. */
 int wave_engine_create(size_t hbm_budget_bytes, int max_slots, void** engine);
+/* Per-step bytes (two FP32 levels and v^2 dt^2) of the shots stepped together in
+ * one group; 0 restores the default. Applies from the next change of the set of
+ * resident shots. */
+int wave_engine_set_group_bytes(void* engine, size_t bytes);
 /* Queue a request; its inputs are copied. WAVE_EBUSY if it can never fit the
  * budget; validation errors as for wave_forward. *id identifies it. */
 int wave_engine_submit(void* engine, const wave_request* req, uint64_t* id);

@@ -51,6 +51,12 @@ bool grid_ok(const wave_grid* g) {
   const int st = g->storage & ~WAVE_STORE_DIFF;
   if (st != WAVE_STORE_F32 && st != WAVE_STORE_F16 && st != WAVE_STORE_BF16) return false;
   if (st == WAVE_STORE_F32 && (g->storage & WAVE_STORE_DIFF)) return false;
+  if (g->path & ~(WAVE_PATH_ONE_STEP | WAVE_PATH_TWO_STEP | WAVE_PATH_STREAM |
+                  WAVE_PATH_CACHED | WAVE_PATH_LINEAR))
+    return false;
+  if ((g->path & WAVE_PATH_ONE_STEP) && (g->path & WAVE_PATH_TWO_STEP)) return false;
+  if ((g->path & WAVE_PATH_STREAM) && (g->path & WAVE_PATH_CACHED)) return false;
+  if (g->zchunk < 0 || g->zchunk > MAXZCHUNK) return false;
   const int64_t pitch = (g->nx + 31) / 32 * 32;
   if (pitch * g->ny * (int64_t)g->nz >= ((int64_t)1 << 31)) return false;
   // one FP32 plane must stay below 2 GiB (the kernels' buffer loads use 32-bit offsets)
@@ -67,12 +73,6 @@ Geom make_geom(const wave_grid* g) {
   return G;
 }
 
-int env_int(const char* name, int dflt) {
-  const char* s = std::getenv(name);
-  if (s == nullptr || *s == 0) return dflt;
-  return std::atoi(s);
-}
-
 // z-chunking: floor(512 / tiles per plane) chunks (at least one, of at least 8
 // planes): about 512 workgroups, two per CU, all resident at once, each sweeping one
 // long chunk. Measured on MI355X at SO8, among the chunk lengths tried: 256^3 best at
@@ -85,14 +85,14 @@ int env_int(const char* name, int dflt) {
 // form). The naive 16-bit form (short_chunks) keeps chunks of 8..32 planes for about
 // 512 workgroups, and balanced chunks of about 20 planes, swept in several rounds,
 // for grids that would need more than 1024 workgroups at 32 planes: 546 Gpt/s at
-// 512^3 SO8 against 498 with one long chunk per workgroup. WAVE_ZCHUNK overrides the
-// chunk length (tuning sweeps).
+// 512^3 SO8 against 498 with one long chunk per workgroup. A positive zchunk fixes
+// the chunk length (the grid's zchunk, or the caller's policy).
 Tiling make_tiling(const Geom& G, int zchunk, bool short_chunks) {
   Tiling T;
   T.ntile_x = (G.nx + TX - 1) / TX;
   T.ntile_y = (G.ny + TY - 1) / TY;
   const int bxy = T.ntile_x * T.ntile_y;
-  int zc = zchunk > 0 ? zchunk : env_int("WAVE_ZCHUNK", 0);
+  int zc = zchunk;
   if (zc <= 0 && short_chunks) {
     const int want = std::max(1, (512 + bxy - 1) / bxy);
     zc = std::min(std::max((G.nz + want - 1) / want, 8), 32);
@@ -348,20 +348,19 @@ bool fused_tiling_ok(const Ctx& C) { return C.L.fused && C.T.zchunk >= C.g->so; 
 // +14 % at 448^3, +23 % at 512^3; SO6 -11 % at 320^3, -14 % at 384^3, +6 % at 448^3,
 // +11 % at 512^3; SO8 (158 registers per lane, one 512-thread workgroup per CU) -10 %
 // at 512^3. Below these sizes the one-step kernel's working set is largely served by
-// the 256 MiB Infinity Cache; longer two-step chunks (128, 256 planes) lost at SO2/SO4. Auto: radius r <= 3 and at least kFusedMinPoints[r]
-// grid points. WAVE_FUSED=1 forces it (radius <= 4; z-chunks of the one-step policy
-// unless WAVE_F2_ZCHUNK is set), 0 disables it.
+// the 256 MiB Infinity Cache; longer two-step chunks (128, 256 planes) lost at
+// SO2/SO4. Chosen by the library: radius r <= 3 and at least kFusedMinPoints[r] grid
+// points. WAVE_PATH_TWO_STEP asks for it at radius <= 4, WAVE_PATH_ONE_STEP never
+// takes it; its z-chunks are the grid's zchunk, else kFusedZChunk planes.
 constexpr int64_t kFusedMinPoints[4] = {0, 30000000, 60000000, 80000000};
 constexpr int kFusedZChunk = 64;
 bool want_fused(const wave_grid* g, int* zchunk) {
-  const int force = env_int("WAVE_FUSED", -1);
-  *zchunk = env_int("WAVE_F2_ZCHUNK", 0);
+  *zchunk = g->zchunk > 0 ? g->zchunk : kFusedZChunk;
   if (store_kind(g) != WAVE_STORE_F32 || g->so / 2 > 4) return false;
-  if (force >= 0) return force != 0;
+  if (g->path & WAVE_PATH_ONE_STEP) return false;
+  if (g->path & WAVE_PATH_TWO_STEP) return true;
   const int64_t npts = (int64_t)g->nx * g->ny * g->nz;
-  if (g->so / 2 > 3 || npts < kFusedMinPoints[g->so / 2]) return false;
-  if (*zchunk == 0) *zchunk = kFusedZChunk;
-  return true;
+  return g->so / 2 <= 3 && npts >= kFusedMinPoints[g->so / 2];
 }
 
 // Source tables of the two-step kernel: for every tile, the grid points of its
@@ -531,7 +530,8 @@ int init_ctx(Ctx& C, const wave_grid* g, int nsrc, int nrec, int mode, int ckpt_
              size_t ws_bytes, void* stream, int zchunk) {
   C.g = g;
   C.G = make_geom(g);
-  C.T = make_tiling(C.G, zchunk, store_kind(g) != WAVE_STORE_F32 && !store_diff(g));
+  C.T = make_tiling(C.G, zchunk > 0 ? zchunk : g->zchunk,
+                    store_kind(g) != WAVE_STORE_F32 && !store_diff(g));
   C.L = make_layout(g, nsrc, nrec, mode, ckpt_every);
   if (ws == nullptr || (reinterpret_cast<uintptr_t>(ws) % kAlign) != 0) return WAVE_EINVAL;
   if (ws_bytes < C.L.total) return WAVE_ENOMEM;
@@ -540,12 +540,13 @@ int init_ctx(Ctx& C, const wave_grid* g, int nsrc, int nrec, int mode, int ckpt_
   // Non-temporal hints on the streamed arrays when one step's fields (v^2 dt^2 and
   // the stored levels) exceed the 256 MiB Infinity Cache: measured on MI355X at
   // 512^3 they gain ~10 %; below it the cache serves the next step's reads and the
-  // hints lose ~20 %. WAVE_NT=0/1 overrides (tuning).
+  // hints lose ~20 %. WAVE_PATH_STREAM / WAVE_PATH_CACHED decide instead.
   {
     const size_t es = store_kind(g) == WAVE_STORE_F32 ? 4 : 2;
     const size_t ws_bytes_step = (size_t)C.G.nfield * (4 + es * (store_diff(g) ? 3 : 2));
-    const int force = env_int("WAVE_NT", -1);
-    C.nt = force >= 0 ? force != 0 : ws_bytes_step > ((size_t)256 << 20);
+    C.nt = (g->path & WAVE_PATH_STREAM)   ? true
+           : (g->path & WAVE_PATH_CACHED) ? false
+                                          : ws_bytes_step > ((size_t)256 << 20);
   }
   double w[MAXR + 1];
   fd_weights(g->so, w);
@@ -629,7 +630,7 @@ StepArgs base_args(const Ctx& C) {
   a.nchunk = C.T.nchunk;
   a.zchunk = C.T.zchunk;
   a.nstencil_blocks = C.T.nblocks;
-  a.xcd_remap = env_int("WAVE_XCD_REMAP", 1) != 0;
+  a.xcd_remap = (C.g->path & WAVE_PATH_LINEAR) == 0;
   for (int q = 0; q <= MAXR; ++q) {
     a.wx[q] = (float)C.wx[q];
     a.wy[q] = (float)C.wy[q];
@@ -776,6 +777,67 @@ int forward_fused(Ctx& C, const float* wavelet, int nsrc, int nrec, float* rec_o
   return WAVE_OK;
 }
 
+// Forward solve behind wave_forward (basic = false) and the unfactorised ablation
+// (basic = true: FP32 storage, SO 8/12/16/24, one step per launch).
+int forward_impl(const wave_grid* g, const float* vel, const float* wavelet,
+                 const double* src_xyz_h, int nsrc, const double* rec_xyz_h, int nrec,
+                 float* rec_out, const float* u0, const float* um1, float* u_final, float* ckpt,
+                 int ckpt_every, void* workspace, size_t ws_bytes, void* hip_stream, bool basic) {
+  int st = validate(g);
+  if (st) return st;
+  if (vel == nullptr || nsrc < 0 || nrec < 0) return WAVE_EINVAL;
+  if (nsrc > 0 && wavelet == nullptr && g->nt > 0) return WAVE_EINVAL;
+  if (nrec > 0 && rec_out == nullptr && g->nt > 0) return WAVE_EINVAL;
+  if (!points_ok(g, src_xyz_h, nsrc) || !points_ok(g, rec_xyz_h, nrec)) return WAVE_EINVAL;
+  if (ckpt != nullptr && ckpt_every <= 0) return WAVE_EINVAL;
+  if (ckpt != nullptr && store_kind(g) != WAVE_STORE_F32) return WAVE_EINVAL;
+  if (basic && (g->storage != WAVE_STORE_F32 ||
+                (g->so != 8 && g->so != 12 && g->so != 16 && g->so != 24)))
+    return WAVE_EINVAL;
+  int fz = 0;
+  const bool fused = !basic && ckpt == nullptr && want_fused(g, &fz);
+  Ctx C;
+  st = setup(C, g, vel, src_xyz_h, nsrc, rec_xyz_h, nrec, WAVE_MODE_FORWARD, 0, workspace,
+             ws_bytes, hip_stream, fused ? fz : 0);
+  if (st) return st;
+  if (store_kind(g) != WAVE_STORE_F32)
+    return forward_reduced(C, wavelet, nsrc, nrec, rec_out, u0, um1, u_final);
+  if (fused && fused_tiling_ok(C))
+    return forward_fused(C, wavelet, nsrc, nrec, rec_out, u0, um1, u_final);
+  float* X[2] = {C.at<float>(C.L.u[0]), C.at<float>(C.L.u[1])};
+  HIP_TRY(launch_pack(u0, X[0], C.G, C.s));
+  HIP_TRY(launch_pack(um1, X[1], C.G, C.s));
+  const int64_t N = (int64_t)g->nx * g->ny * g->nz;
+  StepArgs a = base_args(C);
+  const int r = g->so / 2;
+  for (int n = 0; n < g->nt; ++n) {
+    float* cur = X[n & 1];
+    float* prev = X[(n + 1) & 1];
+    if (ckpt != nullptr && n % ckpt_every == 0) {
+      const int64_t k = n / ckpt_every;
+      HIP_TRY(launch_unpack(cur, ckpt + (2 * k) * N, C.G, C.s));
+      HIP_TRY(launch_unpack(prev, ckpt + (2 * k + 1) * N, C.G, C.s));
+    }
+    a.cur = cur;
+    a.prev = prev;
+    a.out = prev;
+    set_inj(a, C, 0, nsrc, nsrc > 0 ? wavelet + (int64_t)n * nsrc : nullptr);
+    set_samp(a, C, 1, nrec, n >= 1 && nrec > 0 ? rec_out + (int64_t)(n - 1) * nrec : nullptr);
+    if (basic)
+      HIP_TRY(launch_step_basic(a, r, C.s));
+    else
+      HIP_TRY(launch_step(a, r, false, ST_F32, false, C.nt, C.s));
+  }
+  if (nrec > 0 && g->nt > 0) {
+    const PointTables& P = C.L.pts[1];
+    HIP_TRY(launch_sample(X[g->nt & 1], ST_F32, LevelMeta{}, g->nt, C.at<int>(P.samp_idx),
+                          C.at<float>(P.samp_w), nrec, rec_out + (int64_t)(g->nt - 1) * nrec,
+                          C.s));
+  }
+  if (u_final != nullptr) HIP_TRY(launch_unpack(X[g->nt & 1], u_final, C.G, C.s));
+  return WAVE_OK;
+}
+
 int validate(const wave_grid* g) {
   if (!grid_ok(g)) return WAVE_EINVAL;
   const double dtm = wave_cfl_dt_max(g->so, g->vmax, g->hx, g->hy, g->hz);
@@ -822,6 +884,7 @@ const char* wave_status_string(int status) {
     case WAVE_EDEVICE: return "HIP runtime error";
     case WAVE_EBUSY: return "over the memory budget";
     case WAVE_EAGAIN: return "not ready";
+    case WAVE_ELIMIT: return "larger than the static scratch";
     default: return "unknown status";
   }
 }
@@ -832,60 +895,17 @@ int wave_forward(const wave_grid* g, const float* vel, const float* wavelet,
                  const double* src_xyz_h, int nsrc, const double* rec_xyz_h, int nrec,
                  float* rec_out, const float* u0, const float* um1, float* u_final, float* ckpt,
                  int ckpt_every, void* workspace, size_t ws_bytes, void* hip_stream) {
-  int st = validate(g);
-  if (st) return st;
-  if (vel == nullptr || nsrc < 0 || nrec < 0) return WAVE_EINVAL;
-  if (nsrc > 0 && wavelet == nullptr && g->nt > 0) return WAVE_EINVAL;
-  if (nrec > 0 && rec_out == nullptr && g->nt > 0) return WAVE_EINVAL;
-  if (!points_ok(g, src_xyz_h, nsrc) || !points_ok(g, rec_xyz_h, nrec)) return WAVE_EINVAL;
-  if (ckpt != nullptr && ckpt_every <= 0) return WAVE_EINVAL;
-  if (ckpt != nullptr && store_kind(g) != WAVE_STORE_F32) return WAVE_EINVAL;
-  // WAVE_BASIC=1: the unfactorised ablation kernel (SO 8, 12, 16, 24; one step per
-  // launch; comparison with the paper's basic/aggressive experiment only)
-  const bool basic = store_kind(g) == WAVE_STORE_F32 && env_int("WAVE_BASIC", 0) != 0;
-  if (basic && g->so != 8 && g->so != 12 && g->so != 16 && g->so != 24) return WAVE_EINVAL;
-  int fz = 0;
-  const bool fused = !basic && ckpt == nullptr && want_fused(g, &fz);
-  Ctx C;
-  st = setup(C, g, vel, src_xyz_h, nsrc, rec_xyz_h, nrec, WAVE_MODE_FORWARD, 0, workspace,
-             ws_bytes, hip_stream, fused ? fz : 0);
-  if (st) return st;
-  if (store_kind(g) != WAVE_STORE_F32)
-    return forward_reduced(C, wavelet, nsrc, nrec, rec_out, u0, um1, u_final);
-  if (fused && fused_tiling_ok(C))
-    return forward_fused(C, wavelet, nsrc, nrec, rec_out, u0, um1, u_final);
-  float* X[2] = {C.at<float>(C.L.u[0]), C.at<float>(C.L.u[1])};
-  HIP_TRY(launch_pack(u0, X[0], C.G, C.s));
-  HIP_TRY(launch_pack(um1, X[1], C.G, C.s));
-  const int64_t N = (int64_t)g->nx * g->ny * g->nz;
-  StepArgs a = base_args(C);
-  const int r = g->so / 2;
-  for (int n = 0; n < g->nt; ++n) {
-    float* cur = X[n & 1];
-    float* prev = X[(n + 1) & 1];
-    if (ckpt != nullptr && n % ckpt_every == 0) {
-      const int64_t k = n / ckpt_every;
-      HIP_TRY(launch_unpack(cur, ckpt + (2 * k) * N, C.G, C.s));
-      HIP_TRY(launch_unpack(prev, ckpt + (2 * k + 1) * N, C.G, C.s));
-    }
-    a.cur = cur;
-    a.prev = prev;
-    a.out = prev;
-    set_inj(a, C, 0, nsrc, nsrc > 0 ? wavelet + (int64_t)n * nsrc : nullptr);
-    set_samp(a, C, 1, nrec, n >= 1 && nrec > 0 ? rec_out + (int64_t)(n - 1) * nrec : nullptr);
-    if (basic)
-      HIP_TRY(launch_step_basic(a, r, C.s));
-    else
-      HIP_TRY(launch_step(a, r, false, ST_F32, false, C.nt, C.s));
-  }
-  if (nrec > 0 && g->nt > 0) {
-    const PointTables& P = C.L.pts[1];
-    HIP_TRY(launch_sample(X[g->nt & 1], ST_F32, LevelMeta{}, g->nt, C.at<int>(P.samp_idx),
-                          C.at<float>(P.samp_w), nrec, rec_out + (int64_t)(g->nt - 1) * nrec,
-                          C.s));
-  }
-  if (u_final != nullptr) HIP_TRY(launch_unpack(X[g->nt & 1], u_final, C.G, C.s));
-  return WAVE_OK;
+  return forward_impl(g, vel, wavelet, src_xyz_h, nsrc, rec_xyz_h, nrec, rec_out, u0, um1,
+                      u_final, ckpt, ckpt_every, workspace, ws_bytes, hip_stream, false);
+}
+
+int wave_forward_unfactorised(const wave_grid* g, const float* vel, const float* wavelet,
+                              const double* src_xyz_h, int nsrc, const double* rec_xyz_h,
+                              int nrec, float* rec_out, const float* u0, const float* um1,
+                              float* u_final, void* workspace, size_t ws_bytes,
+                              void* hip_stream) {
+  return forward_impl(g, vel, wavelet, src_xyz_h, nsrc, rec_xyz_h, nrec, rec_out, u0, um1,
+                      u_final, nullptr, 0, workspace, ws_bytes, hip_stream, true);
 }
 
 int wave_adjoint(const wave_grid* g, const float* vel, const float* rec_data,

@@ -49,7 +49,7 @@ constexpr double kUpdateRate = 250e9;  // grid-point updates per second, for tha
 constexpr int kEngineZChunk = 32;      // z-chunk length of resident shots
 // Shots stepped together in one run of kReplaySteps launches: their per-step arrays
 // (two levels and v^2 dt^2) fit the 256 MB Infinity Cache together, so they stay
-// cache-resident across the run's steps. WAVE_ENGINE_GROUP_MB overrides (tests).
+// cache-resident across the run's steps. wave_engine_set_group_bytes overrides.
 constexpr size_t kCacheGroupBytes = (size_t)224 << 20;
 
 double now_s() {
@@ -92,6 +92,8 @@ size_t shot_bytes(const wave_grid* g, int nsrc, int nrec) {
 class Engine {
  public:
   Engine(size_t budget, int max_slots) : budget_(budget), max_slots_(max_slots), alloc_(budget) {}
+
+  void set_group_bytes(size_t b) { group_bytes_.store(b); }
 
   int init() {
     HIP_TRY(hipGetDevice(&device_));
@@ -395,7 +397,7 @@ class Engine {
     // engine tiles every shot with 32-plane z-chunks (fewer priming re-reads than
     // the single-solve policy gives small grids; the values do not depend on it).
     int st = init_ctx(s->C, g, s->nsrc, s->nrec, WAVE_MODE_FORWARD, 0, base, s->bytes, s_up_,
-                      kEngineZChunk);
+                      g->zchunk > 0 ? g->zchunk : kEngineZChunk);
     if (st) return st;
     s->C.g = &s->g;
     s->off_wav = s->C.L.total;
@@ -448,9 +450,8 @@ class Engine {
       size_t bytes;
       std::vector<BatchEntry> e;
     };
-    const char* env = std::getenv("WAVE_ENGINE_GROUP_MB");
-    const size_t cap = env != nullptr && std::atoi(env) > 0 ? (size_t)std::atoi(env) << 20
-                                                            : kCacheGroupBytes;
+    const size_t gb = group_bytes_.load();
+    const size_t cap = gb > 0 ? gb : kCacheGroupBytes;
     std::vector<Group> groups;
     std::vector<int> slots;
     for (Shot* s : active) {
@@ -544,6 +545,7 @@ class Engine {
 
   size_t budget_;
   int max_slots_;
+  std::atomic<size_t> group_bytes_{0};
   int device_ = 0;
   void* pool_ = nullptr;
   PoolAlloc alloc_;
@@ -614,6 +616,12 @@ int wave_engine_drain(void* engine, double timeout_s) {
 }
 
 void wave_engine_destroy(void* engine) { delete static_cast<Engine*>(engine); }
+
+int wave_engine_set_group_bytes(void* engine, size_t bytes) {
+  if (engine == nullptr) return WAVE_EINVAL;
+  static_cast<Engine*>(engine)->set_group_bytes(bytes);
+  return WAVE_OK;
+}
 
 size_t wave_engine_request_bytes(const wave_grid* g, int nsrc, int nrec) {
   if (!wave::grid_ok(g) || nsrc < 0 || nrec < 0) return 0;

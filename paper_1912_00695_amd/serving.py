@@ -61,6 +61,8 @@ def _bind():
         L.wave_engine_request_bytes.argtypes = [ctypes.POINTER(wave.WaveGrid), ctypes.c_int,
                                                 ctypes.c_int]
         L.wave_engine_request_bytes.restype = ctypes.c_size_t
+        L.wave_engine_set_group_bytes.argtypes = [vp, ctypes.c_size_t]
+        L.wave_engine_set_group_bytes.restype = ctypes.c_int
         _bound = True
     return L
 
@@ -106,6 +108,12 @@ class Engine:
             raise wave.WaveError(st, "wave_engine_submit")
         self._out[rid.value] = out
         return rid.value, out
+
+    def set_group_bytes(self, nbytes):
+        """Per-step bytes of the shots stepped together in one cache group (0: default)."""
+        st = _bind().wave_engine_set_group_bytes(self._h, int(nbytes))
+        if st != wave.OK:
+            raise wave.WaveError(st, "wave_engine_set_group_bytes")
 
     def poll(self, rid):
         res = WaveResult()

@@ -2,7 +2,8 @@
 
 Argument marshalling only: tensors are passed as device pointers, coordinates
 as host float64 arrays, and every step of the solve runs in the HIP library on
-the caller's current torch stream. PyTorch provides device memory and streams.
+the given stream (default: torch's current stream). PyTorch provides device
+memory and streams.
 If libwave.so has not been built, every entry point raises.
 """
 import ctypes
@@ -14,13 +15,16 @@ import torch
 HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libwave.so")
 
-OK, EINVAL, ECFL, ENOMEM, EDEVICE, EBUSY, EAGAIN = 0, -1, -2, -3, -4, -5, -6
+OK, EINVAL, ECFL, ENOMEM, EDEVICE, EBUSY, EAGAIN, ELIMIT = 0, -1, -2, -3, -4, -5, -6, -7
 STORE_F32, STORE_F16, STORE_BF16, STORE_DIFF = 0, 1, 2, 16
 MODE_FORWARD, MODE_ADJOINT, MODE_GRADIENT = 0, 1, 2
+# execution-path flags (kernels, launch shapes, cache hints; never the arithmetic)
+PATH_ONE_STEP, PATH_TWO_STEP, PATH_STREAM, PATH_CACHED, PATH_LINEAR = 1, 2, 4, 8, 16
 
 # Entry points declared in include/wave.h.
 SYMBOLS = ["wave_cfl_dt_max", "wave_workspace_bytes", "wave_checkpoint_bytes", "wave_forward",
-           "wave_adjoint", "wave_gradient", "wave_rtm", "wave_status_string", "wave_version"]
+           "wave_forward_unfactorised", "wave_adjoint", "wave_gradient", "wave_rtm",
+           "wave_status_string", "wave_version"]
 
 
 class WaveError(RuntimeError):
@@ -35,7 +39,8 @@ class WaveGrid(ctypes.Structure):
                 ("hx", ctypes.c_double), ("hy", ctypes.c_double), ("hz", ctypes.c_double),
                 ("so", ctypes.c_int32), ("dt", ctypes.c_double), ("nt", ctypes.c_int32),
                 ("nbl", ctypes.c_int32 * 6), ("vmax", ctypes.c_double),
-                ("storage", ctypes.c_int32)]
+                ("storage", ctypes.c_int32), ("path", ctypes.c_int32),
+                ("zchunk", ctypes.c_int32)]
 
     @property
     def shape(self):
@@ -64,6 +69,9 @@ def lib():
         L.wave_checkpoint_bytes.restype = sz
         L.wave_forward.argtypes = [gp, fp, fp, dp, i, dp, i, fp, fp, fp, fp, fp, i, vp, sz, vp]
         L.wave_forward.restype = i
+        L.wave_forward_unfactorised.argtypes = [gp, fp, fp, dp, i, dp, i, fp, fp, fp, fp, vp,
+                                                sz, vp]
+        L.wave_forward_unfactorised.restype = i
         L.wave_adjoint.argtypes = [gp, fp, fp, dp, i, dp, i, fp, fp, vp, sz, vp]
         L.wave_adjoint.restype = i
         L.wave_gradient.argtypes = [gp, fp, fp, dp, i, dp, i, fp, fp, i, fp, fp, vp, sz, vp]
@@ -78,8 +86,10 @@ def lib():
     return _lib
 
 
-def make_grid(n, h, so, dt, nt, nbl=(0,) * 6, vmax=None, storage=STORE_F32):
-    """n = (nx, ny, nz), h = (hx, hy, hz) metres, vmax = velocity bound (m/s)."""
+def make_grid(n, h, so, dt, nt, nbl=(0,) * 6, vmax=None, storage=STORE_F32, path=0,
+              zchunk=0):
+    """n = (nx, ny, nz), h = (hx, hy, hz) metres, vmax = velocity bound (m/s); path
+    (PATH_* flags) and zchunk choose the execution path (0: the library's choice)."""
     if vmax is None:
         raise ValueError("vmax (an upper bound of the velocity) is required")
     g = WaveGrid()
@@ -90,6 +100,8 @@ def make_grid(n, h, so, dt, nt, nbl=(0,) * 6, vmax=None, storage=STORE_F32):
         g.nbl[k] = int(v)
     g.vmax = float(vmax)
     g.storage = int(storage)
+    g.path = int(path)
+    g.zchunk = int(zchunk)
     return g
 
 
@@ -140,15 +152,38 @@ def _workspace(nbytes, device, workspace):
     return torch.empty(max(int(nbytes), 1), dtype=torch.uint8, device=device)
 
 
-def _stream(device, stream):
-    s = stream if stream is not None else torch.cuda.current_stream(device)
+def _device_of(vel):
+    if not (isinstance(vel, torch.Tensor) and vel.is_cuda):
+        raise TypeError("vel must be a float32 CUDA tensor")
+    return vel.device
+
+
+def _on(device, stream):
+    """The stream a call runs on: `stream`, else torch's current stream of device.
+    Every temporary, input copy, output and workspace of the call is allocated (and
+    every copy made) while that stream is current, so torch's caching allocator
+    orders their reuse after the call's work on it."""
+    return stream if stream is not None else torch.cuda.current_stream(device)
+
+
+def _sptr(s):
     return ctypes.c_void_p(s.cuda_stream)
 
 
 def forward(grid, vel, wavelet=None, src_xyz=None, rec_xyz=None, u0=None, um1=None,
-            want_final=False, ckpt_every=0, workspace=None, stream=None, rec_out=None):
+            want_final=False, ckpt_every=0, workspace=None, stream=None, rec_out=None,
+            unfactorised=False):
     """Forward solve. Returns dict(rec=[nt][nrec], u_final=[nz][ny][nx] or None,
-    ckpt=[nck][2][nz][ny][nx] or None)."""
+    ckpt=[nck][2][nz][ny][nx] or None). unfactorised=True runs the ablation entry
+    point wave_forward_unfactorised (no checkpoints)."""
+    s = _on(_device_of(vel), stream)
+    with torch.cuda.stream(s):
+        return _forward(grid, vel, wavelet, src_xyz, rec_xyz, u0, um1, want_final, ckpt_every,
+                        workspace, s, rec_out, unfactorised)
+
+
+def _forward(grid, vel, wavelet, src_xyz, rec_xyz, u0, um1, want_final, ckpt_every, workspace,
+             s, rec_out, unfactorised):
     vel = _dev_f32(vel, grid.shape, "vel")
     dev = vel.device
     src = _host_xyz(src_xyz)
@@ -168,17 +203,34 @@ def forward(grid, vel, wavelet=None, src_xyz=None, rec_xyz=None, u0=None, um1=No
     if nbytes == 0:
         raise WaveError(EINVAL, "wave_workspace_bytes")
     ws = _workspace(nbytes, dev, workspace)
-    st = lib().wave_forward(ctypes.byref(grid), _ptr(vel), _ptr(wav), _hptr(src), ns, _hptr(rec),
-                            nr, _ptr(rec_out) if nr else None, _ptr(u0), _ptr(um1), _ptr(uf),
-                            _ptr(ck), int(ckpt_every), _ptr(ws), ws.numel(), _stream(dev, stream))
-    if st != OK:
-        raise WaveError(st, "wave_forward")
+    if unfactorised:
+        if ck is not None:
+            raise WaveError(EINVAL, "wave_forward_unfactorised: no checkpoints")
+        st = lib().wave_forward_unfactorised(
+            ctypes.byref(grid), _ptr(vel), _ptr(wav), _hptr(src), ns, _hptr(rec), nr,
+            _ptr(rec_out) if nr else None, _ptr(u0), _ptr(um1), _ptr(uf), _ptr(ws), ws.numel(),
+            _sptr(s))
+        if st != OK:
+            raise WaveError(st, "wave_forward_unfactorised")
+    else:
+        st = lib().wave_forward(ctypes.byref(grid), _ptr(vel), _ptr(wav), _hptr(src), ns,
+                                _hptr(rec), nr, _ptr(rec_out) if nr else None, _ptr(u0),
+                                _ptr(um1), _ptr(uf), _ptr(ck), int(ckpt_every), _ptr(ws),
+                                ws.numel(), _sptr(s))
+        if st != OK:
+            raise WaveError(st, "wave_forward")
     return {"rec": rec_out, "u_final": uf, "ckpt": ck}
 
 
 def adjoint(grid, vel, rec_data, rec_xyz, src_xyz, want_final=False, workspace=None,
             stream=None):
     """Backward solve (transpose of forward). Returns dict(src=[nt][nsrc], lam_final)."""
+    s = _on(_device_of(vel), stream)
+    with torch.cuda.stream(s):
+        return _adjoint(grid, vel, rec_data, rec_xyz, src_xyz, want_final, workspace, s)
+
+
+def _adjoint(grid, vel, rec_data, rec_xyz, src_xyz, want_final, workspace, s):
     vel = _dev_f32(vel, grid.shape, "vel")
     dev = vel.device
     src = _host_xyz(src_xyz)
@@ -193,7 +245,7 @@ def adjoint(grid, vel, rec_data, rec_xyz, src_xyz, want_final=False, workspace=N
     ws = _workspace(nbytes, dev, workspace)
     st = lib().wave_adjoint(ctypes.byref(grid), _ptr(vel), _ptr(d), _hptr(rec), nr, _hptr(src), ns,
                             _ptr(out) if ns else None, _ptr(lf), _ptr(ws), ws.numel(),
-                            _stream(dev, stream))
+                            _sptr(s))
     if st != OK:
         raise WaveError(st, "wave_adjoint")
     return {"src": out, "lam_final": lf}
@@ -202,6 +254,14 @@ def adjoint(grid, vel, rec_data, rec_xyz, src_xyz, want_final=False, workspace=N
 def gradient(grid, vel, wavelet, src_xyz, rec_xyz, rec_grad, ckpt=None, ckpt_every=0,
              want_wavelet_grad=True, workspace=None, stream=None):
     """Gradient of L(d) given dL/dd. Returns dict(grad_vel, grad_wavelet)."""
+    s = _on(_device_of(vel), stream)
+    with torch.cuda.stream(s):
+        return _gradient(grid, vel, wavelet, src_xyz, rec_xyz, rec_grad, ckpt, ckpt_every,
+                         want_wavelet_grad, workspace, s)
+
+
+def _gradient(grid, vel, wavelet, src_xyz, rec_xyz, rec_grad, ckpt, ckpt_every,
+              want_wavelet_grad, workspace, s):
     vel = _dev_f32(vel, grid.shape, "vel")
     dev = vel.device
     src = _host_xyz(src_xyz)
@@ -222,7 +282,7 @@ def gradient(grid, vel, wavelet, src_xyz, rec_xyz, rec_grad, ckpt=None, ckpt_eve
     ws = _workspace(nbytes, dev, workspace)
     st = lib().wave_gradient(ctypes.byref(grid), _ptr(vel), _ptr(wav), _hptr(src), ns, _hptr(rec),
                              nr, _ptr(rg), _ptr(ckpt), int(ckpt_every), _ptr(gv), _ptr(gw),
-                             _ptr(ws), ws.numel(), _stream(dev, stream))
+                             _ptr(ws), ws.numel(), _sptr(s))
     if st != OK:
         raise WaveError(st, "wave_gradient")
     return {"grad_vel": gv, "grad_wavelet": gw}
@@ -232,6 +292,13 @@ def rtm(grid, vel, wavelet, src_xyz, rec_xyz, rec_data, ckpt=None, ckpt_every=0,
         stream=None):
     """Zero-lag cross-correlation image sum_n u^n lambda^n of the forward field with the
     backward field driven by rec_data. Returns the image [nz][ny][nx]."""
+    s = _on(_device_of(vel), stream)
+    with torch.cuda.stream(s):
+        return _rtm(grid, vel, wavelet, src_xyz, rec_xyz, rec_data, ckpt, ckpt_every, workspace,
+                    s)
+
+
+def _rtm(grid, vel, wavelet, src_xyz, rec_xyz, rec_data, ckpt, ckpt_every, workspace, s):
     vel = _dev_f32(vel, grid.shape, "vel")
     dev = vel.device
     src = _host_xyz(src_xyz)
@@ -248,7 +315,7 @@ def rtm(grid, vel, wavelet, src_xyz, rec_xyz, rec_data, ckpt=None, ckpt_every=0,
     ws = _workspace(nbytes, dev, workspace)
     st = lib().wave_rtm(ctypes.byref(grid), _ptr(vel), _ptr(wav), _hptr(src), ns, _hptr(rec), nr,
                         _ptr(rd), _ptr(ckpt), int(ckpt_every), _ptr(img), _ptr(ws), ws.numel(),
-                        _stream(dev, stream))
+                        _sptr(s))
     if st != OK:
         raise WaveError(st, "wave_rtm")
     return img

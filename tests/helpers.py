@@ -34,10 +34,10 @@ class Case:
         return oracle.Grid(self.n, self.h, self.so, self.dt, self.nt, nbl=self.nbl,
                            vmax=self.vmax)
 
-    def wgrid(self, storage=0):
+    def wgrid(self, storage=0, path=0, zchunk=0):
         from paper_1912_00695_amd import wave
         return wave.make_grid(self.n, self.h, self.so, self.dt, self.nt, nbl=self.nbl,
-                              vmax=self.vmax, storage=storage)
+                              vmax=self.vmax, storage=storage, path=path, zchunk=zchunk)
 
     def oracle_forward(self):
         return oracle.forward(self.ogrid(), self.vel, self.wavelet, self.src, self.rec,
@@ -85,4 +85,19 @@ def ragged_case(so, nt=50, n=(97, 37, 23), seed=0):
                             inputs.point((64, 16, 11), h)])
     c.u0 = inputs.random_field(c.vel.shape, seed + 3) * 1e-2
     c.um1 = inputs.random_field(c.vel.shape, seed + 4) * 1e-2
+    return c
+
+
+def c4_case(n=(512, 512, 512), nt=1000, nbl=40, rec_stride=1):
+    """SO8, smoothed-random velocity in [1500, 4500] m/s (20-cell correlation,
+    seed 4), 15 Hz Ricker at the centre, dt = 0.5 dt_max(4500), receivers along x
+    through the plane 10 cells below the source and at z = 20 (every rec_stride-th
+    point of each line)."""
+    h = (10.0, 10.0, 10.0)
+    vel = inputs.smooth_random_range(n, 1500.0, 4500.0, 20.0, seed=4)
+    c = Case(n, h, 8, nt, vel, 4500.0, nbl=(nbl,) * 6)
+    c.src = inputs.point((n[0] // 2, n[1] // 2, n[2] // 2), h)
+    c.wavelet = inputs.ricker(15.0, c.dt, nt)[:, None]
+    c.rec = np.concatenate([inputs.line_x(n, h, n[1] // 2, n[2] // 2 + 10)[::rec_stride],
+                            inputs.line_x(n, h, n[1] // 2, 20)[::rec_stride]])
     return c

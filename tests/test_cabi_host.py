@@ -31,7 +31,7 @@ def test_library_exports_every_declared_symbol():
 
 def test_status_strings():
     L = wave.lib()
-    for s in (0, -1, -2, -3, -4, -5, -6):
+    for s in (0, -1, -2, -3, -4, -5, -6, -7):
         assert L.wave_status_string(s)
     assert L.wave_version().startswith(b"wave")
 
@@ -55,7 +55,7 @@ def _grid(**kw):
     d.update(kw)
     dt = d.pop("dt", 0.5 * wave.cfl_dt_max(d["so"], d["vmax"], d["h"]))
     return wave.make_grid(d["n"], d["h"], d["so"], dt, d["nt"], d["nbl"], d["vmax"],
-                          d.get("storage", 0))
+                          d.get("storage", 0), d.get("path", 0), d.get("zchunk", 0))
 
 
 def test_workspace_bytes():
@@ -137,3 +137,36 @@ def test_adjoint_and_gradient_reject_before_enqueue():
                            None, FAKE, 1 << 40, None) == wave.EINVAL  # no grad_vel
     assert L.wave_gradient(ctypes.byref(g), FAKE, FAKE, None, 0, None, 0, FAKE, FAKE, 0, FAKE,
                            None, FAKE, 1 << 40, None) == wave.EINVAL  # ckpt without interval
+
+
+def test_path_flags_validated():
+    """Execution-path flags and the z-chunk length are arguments (no environment
+    variable changes a call): contradictory or unknown flags and chunk lengths out
+    of 0..256 are rejected before anything is enqueued."""
+    for bad in (wave.PATH_ONE_STEP | wave.PATH_TWO_STEP, wave.PATH_STREAM | wave.PATH_CACHED,
+                32, -1):
+        assert _fwd(_grid(path=bad)) == wave.EINVAL, bad
+    for zc in (-1, 257):
+        assert _fwd(_grid(zchunk=zc)) == wave.EINVAL, zc
+    assert wave.workspace_bytes(_grid(zchunk=300), 0, 0) == 0
+    # valid flags pass validation (the call then fails on the workspace size)
+    for ok in (wave.PATH_ONE_STEP, wave.PATH_TWO_STEP | wave.PATH_STREAM | wave.PATH_LINEAR,
+               wave.PATH_CACHED):
+        g = _grid(path=ok, zchunk=7)
+        assert _fwd(g, wsb=wave.workspace_bytes(g, 0, 0) - 1) == wave.ENOMEM
+
+
+def test_unfactorised_rejects_other_orders_and_storage():
+    L = wave.lib()
+    for kw in (dict(so=4), dict(so=10), dict(storage=wave.STORE_F16)):
+        g = _grid(**kw)
+        assert L.wave_forward_unfactorised(ctypes.byref(g), FAKE, None, None, 0, None, 0, None,
+                                           None, None, None, FAKE, 1 << 40, None) == wave.EINVAL
+
+
+def test_no_environment_reads_in_the_library():
+    """The library's sources read no environment variable (execution choices are
+    call arguments)."""
+    import glob
+    for f in glob.glob(os.path.join(ROOT, "paper_1912_00695_amd", "csrc", "*")):
+        assert "getenv" not in open(f).read(), f

@@ -1,15 +1,13 @@
 """The unfactorised ("basic") form of the update, the ablation of the paper's
 basic-versus-aggressive experiment (Section 4, Tables 2-3): every term of the
 Section 2.1 SO2 listing's expression, generalised to the star stencil, with its own
-coefficient and its own division by r0 = dt m + dt^2 damp / 2. Selected with
-WAVE_BASIC=1 (read at every call) for SO 8, 12, 16, 24.
+coefficient and its own division by r0 = dt m + dt^2 damp / 2. It has its own entry
+point, wave_forward_unfactorised, for SO 8, 12, 16, 24.
 
 Tolerance against the FP64 oracle: rel-L2 <= 1e-4. The unfactorised form rounds
 every term separately and does not take the q = 1 pairs about the centre, so it
 carries the FP32 error the factorised kernel avoids (measured here and printed).
 """
-import os
-
 import numpy as np
 import pytest
 
@@ -24,13 +22,9 @@ def _run(case, basic):
     dev = torch.device("cuda:0")
     t = lambda a: None if a is None else torch.from_numpy(
         np.ascontiguousarray(a, dtype=np.float32)).to(dev)
-    os.environ["WAVE_BASIC"] = "1" if basic else "0"
-    try:
-        out = wave.forward(case.wgrid(), t(case.vel), t(case.wavelet), case.src, case.rec,
-                           u0=t(case.u0), um1=t(case.um1), want_final=True)
-        torch.cuda.synchronize()
-    finally:
-        os.environ.pop("WAVE_BASIC", None)
+    out = wave.forward(case.wgrid(), t(case.vel), t(case.wavelet), case.src, case.rec,
+                       u0=t(case.u0), um1=t(case.um1), want_final=True, unfactorised=basic)
+    torch.cuda.synchronize()
     return out["rec"].cpu().numpy(), out["u_final"].cpu().numpy()
 
 
@@ -51,17 +45,5 @@ def test_basic_form_matches_oracle(so):
 def test_basic_form_rejects_other_orders():
     from paper_1912_00695_amd import wave
     case = ragged_case(4, nt=5, seed=60)
-    os.environ["WAVE_BASIC"] = "1"
-    try:
-        with pytest.raises(wave.WaveError):
-            _run_plain(case)
-    finally:
-        os.environ.pop("WAVE_BASIC", None)
-
-
-def _run_plain(case):
-    import torch
-    from paper_1912_00695_amd import wave
-    dev = torch.device("cuda:0")
-    t = lambda a: torch.from_numpy(np.ascontiguousarray(a, dtype=np.float32)).to(dev)
-    return wave.forward(case.wgrid(), t(case.vel), t(case.wavelet), case.src, case.rec)
+    with pytest.raises(wave.WaveError):
+        _run(case, True)

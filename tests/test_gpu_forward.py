@@ -12,7 +12,7 @@ pytestmark = pytest.mark.gpu
 TOL = 1e-5
 
 
-def _run(case, want_final=True, ckpt_every=0):
+def _run(case, want_final=True, ckpt_every=0, path=0, zchunk=0):
     import torch
     from paper_1912_00695_amd import wave
     dev = torch.device("cuda:0")
@@ -23,8 +23,8 @@ def _run(case, want_final=True, ckpt_every=0):
         if case.u0 is not None else None
     um1 = torch.from_numpy(np.ascontiguousarray(case.um1, dtype=np.float32)).to(dev) \
         if case.um1 is not None else None
-    out = wave.forward(case.wgrid(), vel, wav, case.src, case.rec, u0=u0, um1=um1,
-                       want_final=want_final, ckpt_every=ckpt_every)
+    out = wave.forward(case.wgrid(path=path, zchunk=zchunk), vel, wav, case.src, case.rec,
+                       u0=u0, um1=um1, want_final=want_final, ckpt_every=ckpt_every)
     torch.cuda.synchronize()
     res = {k: (v.cpu().numpy() if v is not None else None) for k, v in out.items()}
     return res
@@ -200,20 +200,14 @@ def test_chunk_lengths_give_identical_results(so):
     and the LDS ring that holds them only change when values are fetched), so traces
     and final field are bitwise equal; the default run is also checked against the
     oracle."""
-    import os
     case = ragged_case(so, nt=30, seed=60 + so)
     _oracle_inputs(case)
     print("chunk lengths SO", so, flush=True)
-    os.environ.pop("WAVE_ZCHUNK", None)
     ref = _run(case)
     rec, uf, _ = case.oracle_forward()
     assert rel_l2(ref["u_final"], uf) <= TOL and rel_l2(ref["rec"], rec) <= TOL
     for zc in (1, 2, 5, 23):
-        os.environ["WAVE_ZCHUNK"] = str(zc)
-        try:
-            g = _run(case)
-        finally:
-            del os.environ["WAVE_ZCHUNK"]
+        g = _run(case, zchunk=zc)
         print("  zchunk", zc, "field equal", np.array_equal(g["u_final"], ref["u_final"]),
               flush=True)
         assert np.array_equal(g["u_final"], ref["u_final"])

@@ -4,15 +4,13 @@ and against the one-step-per-launch path of the same library.
 wave_forward can take the two-step path for FP32 storage, radius <= 4, no
 checkpoints and z-chunks of at least 2r planes; by default it does so only where it
 is faster (SO2/4/6 from 3e7/6e7/8e7 grid points, with 64-plane chunks). These
-tests force it with WAVE_FUSED=1 (chunks of the one-step policy, so the small cases
-cross chunk boundaries) and select the single-step path with WAVE_FUSED=0 (the
-variables are read at every call). Tolerances: rel-L2 <= 1e-5 against the oracle
+tests ask for it with the grid's path WAVE_PATH_TWO_STEP and 8-plane z-chunks (so
+the small cases cross chunk boundaries) and for the single-step path with
+WAVE_PATH_ONE_STEP. Tolerances: rel-L2 <= 1e-5 against the oracle
 on traces and final field (FP32 vs FP64), <= 1e-6 between the two GPU paths (both
 evaluate every point's update with the same expression; the bound allows for the
 compiler contracting differently in the two kernels).
 """
-import os
-
 import numpy as np
 import pytest
 
@@ -22,23 +20,16 @@ from paper_1912_00695_amd import inputs
 pytestmark = pytest.mark.gpu
 
 
-def _run(case, fused=True):
+def _run(case, fused=True, zchunk=8):
     import torch
     from paper_1912_00695_amd import wave
     dev = torch.device("cuda:0")
     t = lambda a: None if a is None else torch.from_numpy(
         np.ascontiguousarray(a, dtype=np.float32)).to(dev)
-    old = os.environ.get("WAVE_FUSED")
-    os.environ["WAVE_FUSED"] = "1" if fused else "0"
-    try:
-        out = wave.forward(case.wgrid(), t(case.vel), t(case.wavelet), case.src, case.rec,
-                           u0=t(case.u0), um1=t(case.um1), want_final=True)
-        torch.cuda.synchronize()
-    finally:
-        if old is None:
-            del os.environ["WAVE_FUSED"]
-        else:
-            os.environ["WAVE_FUSED"] = old
+    path = wave.PATH_TWO_STEP if fused else wave.PATH_ONE_STEP
+    out = wave.forward(case.wgrid(path=path, zchunk=zchunk), t(case.vel), t(case.wavelet),
+                       case.src, case.rec, u0=t(case.u0), um1=t(case.um1), want_final=True)
+    torch.cuda.synchronize()
     rec = out["rec"].cpu().numpy() if out.get("rec") is not None else np.zeros((case.nt, 0))
     return rec, out["u_final"].cpu().numpy()
 
@@ -67,7 +58,7 @@ def test_fused_equals_single_step_path(so):
 
 def test_fused_sources_on_tile_and_chunk_edges():
     """Sources and receivers on and next to tile edges (x = 63, 64; y = 15, 16) and
-    z-chunk edges (z = 31, 32 with 32-plane chunks), where the extended-region
+    z-chunk edges (z = 31, 32 with 8-plane chunks), where the extended-region
     injection tables of neighbouring tiles overlap; SO8, 160 x 48 x 70."""
     n, h = (160, 48, 70), (10.0, 10.0, 10.0)
     vel = inputs.smooth_random_range(n, 1500.0, 2500.0, 8.0, seed=31)
@@ -112,19 +103,14 @@ def test_fused_full_size_512_so4_matches_single_step():
     c.wavelet = inputs.ricker(10.0, c.dt, nt)[:, None]
     c.rec = inputs.line_x(n, h, 256, 260)
     print("512^3 SO4 default (two-step) vs one-step", flush=True)
-    os.environ.pop("WAVE_FUSED", None)
     dev = torch.device("cuda:0")
     t = lambda a: torch.from_numpy(np.ascontiguousarray(a, dtype=np.float32)).to(dev)
     outs = []
-    for flag in (None, "0"):
-        if flag is not None:
-            os.environ["WAVE_FUSED"] = flag
-        try:
-            o = wave.forward(c.wgrid(), t(c.vel), t(c.wavelet), c.src, c.rec, want_final=True)
-            outs.append((o["rec"].cpu().numpy(), o["u_final"].cpu().numpy()))
-            del o
-        finally:
-            os.environ.pop("WAVE_FUSED", None)
+    for path in (0, wave.PATH_ONE_STEP):
+        o = wave.forward(c.wgrid(path=path), t(c.vel), t(c.wavelet), c.src, c.rec,
+                         want_final=True)
+        outs.append((o["rec"].cpu().numpy(), o["u_final"].cpu().numpy()))
+        del o
     (r1, u1), (r0, u0) = outs
     print("  traces %.3e  field %.3e" % (rel_l2(r1, r0), rel_l2(u1, u0)), flush=True)
     assert np.abs(r0).max() > 0
@@ -145,7 +131,6 @@ def test_fused_full_size_512_so4_matches_oracle():
     c.wavelet = inputs.ricker(15.0, c.dt, nt)[:, None]
     c.rec = np.concatenate([inputs.line_x(n, h, 255, 257), c.src + 25.0])
     print("512^3 SO4 default path vs oracle (%d threads)" % oracle.num_threads(), flush=True)
-    os.environ.pop("WAVE_FUSED", None)
     dev = torch.device("cuda:0")
     t = lambda a: torch.from_numpy(np.ascontiguousarray(a, dtype=np.float32)).to(dev)
     o = wave.forward(c.wgrid(), t(c.vel), t(c.wavelet), c.src, c.rec, want_final=True)

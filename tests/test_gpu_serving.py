@@ -112,24 +112,18 @@ def test_cache_groups_give_identical_results():
     """With a 1 MB cache-group cap every resident shot is stepped in a group of its
     own (16 launches per group, group after group): the traces must be bitwise those
     of the default grouping, in which the whole small mix shares one group."""
-    import os
     reqs = _small_mix(seed=7, count=5)
     outs = {}
     for cap in (None, "1"):
-        if cap is None:
-            os.environ.pop("WAVE_ENGINE_GROUP_MB", None)
-        else:
-            os.environ["WAVE_ENGINE_GROUP_MB"] = cap
-        try:
-            with _engine() as eng:
-                got = [eng.submit(r["grid"], r["vel"], r["wavelet"], r["src"], r["rec"])
-                       for r in reqs]
-                eng.drain(120)
-                st = eng.stats()
-                assert st["completed"] == len(reqs)
-                outs[cap] = [o for _, o in got]
-        finally:
-            os.environ.pop("WAVE_ENGINE_GROUP_MB", None)
+        with _engine() as eng:
+            if cap is not None:
+                eng.set_group_bytes(1 << 20)
+            got = [eng.submit(r["grid"], r["vel"], r["wavelet"], r["src"], r["rec"])
+                   for r in reqs]
+            eng.drain(120)
+            st = eng.stats()
+            assert st["completed"] == len(reqs)
+            outs[cap] = [o for _, o in got]
         print("group cap", cap, "max resident", st["max_resident"], flush=True)
     for a, b in zip(outs[None], outs["1"]):
         assert np.abs(a).max() > 0
