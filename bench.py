@@ -72,7 +72,10 @@ def c2_problem(so, nt=500, n=(256, 256, 256), path=0, zchunk=0):
 
 
 class Solver:
-    """Device-resident inputs and a reusable workspace for repeated solves."""
+    """Device-resident inputs, a reusable workspace and output buffer for repeated
+    solves. With the library's default launch policy a repeated call is replayed
+    from a captured graph; the constructor makes two untimed calls (the second one
+    captures), so timed calls replay."""
 
     def __init__(self, P, dev, unfactorised=False):
         import torch
@@ -84,6 +87,8 @@ class Solver:
         nbytes = wave.workspace_bytes(P["grid"], len(P["src"]), len(P["rec"]))
         self.ws = torch.empty(nbytes, dtype=torch.uint8, device=dev)
         self.unfactorised = unfactorised
+        for _ in range(2):
+            self.run()
 
     def run(self):
         self.wave.forward(self.P["grid"], self.vel, self.wav, self.P["src"], self.P["rec"],
@@ -112,10 +117,70 @@ def time_solves(solver, steps, warmup, per_solve=None):
     return ev[0].elapsed_time(ev[steps]) / 1000.0, wall
 
 
+def small_grid_leg(dev, solves=20):
+    """Launch-bound sizes: the plain case (64^3, h = 10 m, SO4, v = 1500 m/s, no
+    sponge, Gaussian pulse of sigma = 3 cells at rest at the centre, 100 steps; the
+    earlier level is the pulse itself, as timing does not depend on the start) and
+    a 96^3 case of the serving mix (SO4, 20-cell sponge, two-layer 1500/3000 m/s,
+    Ricker source, receiver line, 200 steps). Each solve timed with direct
+    launches and with the graph replay of repeated calls, for the default z-chunks
+    and for 1-plane chunks (the most workgroups)."""
+    import torch
+    from paper_1912_00695_amd import inputs, wave
+    res = {}
+    h = (10.0, 10.0, 10.0)
+    n1 = (64, 64, 64)
+    dt1 = 0.5 * wave.cfl_dt_max(4, 1500.0, h)
+    v1 = torch.from_numpy(inputs.constant(n1, 1500.0)).to(dev)
+    u0 = torch.from_numpy(inputs.gaussian_pulse(n1, (32, 32, 32), 3.0)).to(dev)
+    n2 = (96, 96, 96)
+    dt2 = 0.5 * wave.cfl_dt_max(4, 3000.0, h)
+    v2 = torch.from_numpy(inputs.two_layer(n2, 1500.0, 3000.0, 48)).to(dev)
+    w2 = torch.from_numpy(inputs.ricker(10.0, dt2, 200)[:, None]).to(dev)
+    src2, rec2 = inputs.point((48, 48, 48), h), inputs.line_x(n2, h, 48, 20)
+    for name, zc in (("auto_chunks", 0), ("1_plane_chunks", 1)):
+        for mode, path in (("direct", wave.PATH_DIRECT), ("graph", wave.PATH_GRAPH)):
+            g1 = wave.make_grid(n1, h, 4, dt1, 100, vmax=1500.0, path=path, zchunk=zc)
+            ws1 = torch.empty(wave.workspace_bytes(g1, 0, 0), dtype=torch.uint8, device=dev)
+            uf = torch.empty((64, 64, 64), dtype=torch.float32, device=dev)
+            g2 = wave.make_grid(n2, h, 4, dt2, 200, (20,) * 6, vmax=3000.0, path=path, zchunk=zc)
+            ws2 = torch.empty(wave.workspace_bytes(g2, 1, 96), dtype=torch.uint8, device=dev)
+            r2 = torch.empty((200, 96), dtype=torch.float32, device=dev)
+            cases = (("c1_64cube_so4", 64 ** 3, 100,
+                      lambda: wave.forward(g1, v1, None, None, None, u0=u0, um1=u0,
+                                           workspace=ws1, u_final=uf)),
+                     ("96cube_so4", 96 ** 3, 200,
+                      lambda: wave.forward(g2, v2, w2, src2, rec2, workspace=ws2, rec_out=r2)))
+            for cname, npts, nsteps, fn in cases:
+                upd = npts * nsteps
+                for _ in range(3):
+                    fn()
+                torch.cuda.synchronize()
+                e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+                t0 = time.perf_counter()
+                e0.record()
+                for _ in range(solves):
+                    fn()
+                e1.record()
+                torch.cuda.synchronize()
+                wall = time.perf_counter() - t0
+                el = e0.elapsed_time(e1) / 1000.0
+                res.setdefault(cname, {})["%s_%s" % (name, mode)] = {
+                    "gpts": round(upd * solves / el / 1e9, 2),
+                    "us_per_step": round(el / solves / nsteps * 1e6, 3),
+                    "host_wall_s": round(wall, 4)}
+            del ws1, ws2
+    log("small grids: %s" % res)
+    return res
+
+
 def reduced_precision_leg(dev):
     """512^3 SO8, smoothed-random 1500-4500 m/s, 15 Hz Ricker at the centre, 1000 steps,
-    40-cell sponge: throughput of each wavefield storage format, speedup over FP32
-    storage and rel-L2 of the final field and traces against the FP32 run."""
+    40-cell sponge, receivers at every 4th point of two lines along x (10 cells below
+    the source and at z = 20): throughput of each wavefield storage format, speedup
+    over FP32 storage, rel-L2 of the final field and traces against the FP32 run and,
+    when tests/golden/c4_reference.npz (the FP64 oracle's result of this workload) is
+    present, against the oracle (field on its 64^3 sub-lattice sample)."""
     import numpy as np
     import torch
     from paper_1912_00695_amd import inputs, wave
@@ -125,7 +190,9 @@ def reduced_precision_leg(dev):
     vel = torch.from_numpy(inputs.smooth_random_range(n, 1500.0, 4500.0, 20.0, seed=4)).to(dev)
     wav = torch.from_numpy(inputs.ricker(15.0, dt, nt)[:, None]).to(dev)
     src = inputs.point((256, 256, 256), h)
-    rec = np.concatenate([inputs.line_x(n, h, 256, 266), inputs.line_x(n, h, 256, 20)])
+    rec = np.concatenate([inputs.line_x(n, h, 256, 266)[::4], inputs.line_x(n, h, 256, 20)[::4]])
+    gold = os.path.join(ROOT, "tests", "golden", "c4_reference.npz")
+    gold = np.load(gold, allow_pickle=False) if os.path.exists(gold) else None
     res, ref = {}, None
     for name, st in (("f32", 0), ("f16_diff", 17), ("bf16_diff", 18), ("f16", 1), ("bf16", 2)):
         g = wave.make_grid(n, h, 8, dt, nt, (40,) * 6, vmax=vmax, storage=st)
@@ -146,6 +213,12 @@ def reduced_precision_leg(dev):
         bpp = {0: 16, 1: 10, 2: 10, 17: 12, 18: 12}[st]
         item = {"gpts": round(gp, 2), "alg_bytes_per_pt": bpp,
                 "hbm_frac": round(gp * bpp / HBM_PEAK_GBS, 4)}
+        if gold is not None:
+            smp = u[4::8, 4::8, 4::8].cpu().numpy()
+            gs, gt = gold["sample"].astype(np.float64), gold["traces"].astype(np.float64)
+            item["field_rel_l2_vs_oracle"] = float(np.linalg.norm(smp - gs) / np.linalg.norm(gs))
+            item["traces_rel_l2_vs_oracle"] = float(np.linalg.norm(r.cpu().numpy() - gt) /
+                                                    np.linalg.norm(gt))
         if ref is None:
             ref = (u, r, gp)
         else:
@@ -379,13 +452,19 @@ def main():
                     help="grid points per axis of the timed workload (profiling runs; the "
                          "benchmark line is quoted at 256)")
     ap.add_argument("--nt", type=int, default=500, help="time steps of the timed workload")
+    ap.add_argument("--launch", default="default", choices=["default", "direct", "graph"],
+                    help="launch policy of the timed solves (default: graph replay of "
+                         "repeated calls)")
     ap.add_argument("--no-sweep", action="store_true")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-serving", action="store_true")
-    ap.add_argument("--serving-requests", type=int, default=300,
+    ap.add_argument("--serving-requests", type=int, default=2000,
                     help="requests in the Poisson serving stream (rate 20/s)")
     ap.add_argument("--only-timed", action="store_true",
                     help="run only the timed solves (for profiler runs)")
+    ap.add_argument("--leg", default="",
+                    help="run only this leg after the timed solves and print its JSON "
+                         "(small_grids)")
     ap.add_argument("--with-copy", action="store_true",
                     help="after the timed solves, run a plain 256 MiB device copy three times "
                          "(calibrates profiler byte counters against a known size)")
@@ -403,7 +482,9 @@ def main():
     if (args.n != 256 or args.nt != 500) and not args.only_timed:
         print("--n/--nt change the workload: use them with --only-timed", file=sys.stderr)
         sys.exit(2)
-    P = c2_problem(args.so, nt=args.nt, n=(args.n,) * 3)
+    from paper_1912_00695_amd import wave as _w
+    launch_path = {"default": 0, "direct": _w.PATH_DIRECT, "graph": _w.PATH_GRAPH}[args.launch]
+    P = c2_problem(args.so, nt=args.nt, n=(args.n,) * 3, path=launch_path)
     solver = Solver(P, dev)
     log("timing %d solves of %d^3 SO%d x %d steps (warmup %d)" % (args.steps, args.n, args.so,
                                                                   P["nt"], args.warmup))
@@ -447,7 +528,9 @@ def main():
         torch.cuda.synchronize()
         out["copy_calibration_bytes"] = 2 * x.numel() * 4
         del x, y
-    if args.only_timed:
+    if args.leg == "small_grids":
+        out["small_grids"] = small_grid_leg(dev)
+    if args.only_timed or args.leg:
         print(json.dumps(out), flush=True)
         return
     if not args.no_sweep:
@@ -463,16 +546,17 @@ def main():
         out["so_sweep_256"] = sweep
         # cache-defeating control: 512^3 (4 fields x 537 MB per step, far above the
         # 256 MB Infinity Cache)
-        P5 = c2_problem(8, nt=100, n=(512, 512, 512))
+        P5 = c2_problem(8, nt=500, n=(512, 512, 512))
         S = Solver(P5, dev)
-        e, _ = time_solves(S, 2, 1)
-        g = 512 ** 3 * 100 * 2 / e / 1e9
+        e, _ = time_solves(S, 2, 0)
+        g = 512 ** 3 * 500 * 2 / e / 1e9
         out["control_512_so8"] = {"gpts": round(g, 2),
                                   "hbm_frac": round(g * ALG_BYTES_PER_PT / HBM_PEAK_GBS, 4),
-                                  "nt": 100}
+                                  "nt": 500}
         log("control 512^3 SO8: %.2f Gpt/s" % g)
         del S
     if not args.no_sweep:
+        out["small_grids"] = small_grid_leg(dev)
         out["lowp_512_so8"] = reduced_precision_leg(dev)
         out["two_step_kernel"] = two_step_leg(dev)
         out["basic_vs_factorised_256"] = basic_leg(dev)

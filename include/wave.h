@@ -65,7 +65,6 @@ extern "C" {
 #define WAVE_EDEVICE (-4) /* a HIP runtime call failed                                      */
 #define WAVE_EBUSY (-5)   /* serving engine: request exceeds the memory budget              */
 #define WAVE_EAGAIN (-6)  /* serving engine: result not ready yet                           */
-#define WAVE_ELIMIT (-7)  /* problem larger than the static scratch of wave_forward_noalloc */
 
 /* Wavefield storage formats (arithmetic is FP32 in every format). The 16-bit
  * formats store each level as value * 2^e with a power-of-two scale e chosen per
@@ -93,6 +92,13 @@ extern "C" {
 #define WAVE_PATH_STREAM 4    /* non-temporal hints on the streamed arrays             */
 #define WAVE_PATH_CACHED 8    /* no non-temporal hints                                 */
 #define WAVE_PATH_LINEAR 16   /* workgroups in plain tile order (no XCD-aware order)   */
+/* The time loop's launches are recorded per call. By default a call whose launches
+ * equal (same arguments, same device) those of an earlier call is captured into a
+ * HIP graph, kept in a cache of the library (16 graphs, least recently used
+ * replaced; the HIP runtime holds their memory), and replayed on hip_stream from
+ * then on. The replay runs the same kernels with the same arguments. */
+#define WAVE_PATH_GRAPH 32    /* capture and replay from the first call               */
+#define WAVE_PATH_DIRECT 64   /* always launch directly (no graph)                     */
 
 /* Workspace modes for wave_workspace_bytes(). */
 #define WAVE_MODE_FORWARD 0
@@ -113,7 +119,8 @@ typedef struct {
   int32_t storage;     /* WAVE_STORE_F32 | WAVE_STORE_F16 | WAVE_STORE_BF16, the last two
                           optionally | WAVE_STORE_DIFF                               */
   int32_t path;        /* WAVE_PATH_* flags (0 = chosen by the library); ONE_STEP with
-                          TWO_STEP, STREAM with CACHED, or unknown bits: WAVE_EINVAL */
+                          TWO_STEP, STREAM with CACHED, GRAPH with DIRECT, or unknown
+                          bits: WAVE_EINVAL                                          */
   int32_t zchunk;      /* planes per z-chunk of the stencil sweep, 1..256 (0 = chosen
                           by the library: about 512 workgroups; 64 planes for the
                           two-step kernel); results do not depend on it              */

@@ -11,7 +11,8 @@ import sys
 HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libwave.so")
-SOURCES = ["wave_kernels.hip", "wave_fused.hip", "wave_api.cpp", "wave_engine.cpp"]
+SOURCES = ["wave_kernels.hip", "wave_fused.hip", "wave_api.cpp", "wave_engine.cpp",
+           "wave_launch.cpp"]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 COMMON = ["-O3", "-std=c++17", "-fPIC", "-Wall", "-ffp-contract=fast",
@@ -21,17 +22,23 @@ COMMON = ["-O3", "-std=c++17", "-fPIC", "-Wall", "-ffp-contract=fast",
 def build(verbose: bool = False, lib: str = LIB, defines=()) -> str:
     """Compile and link; defines are extra -D options (tuning switches such as
     WAVE_ZUNROLL_MASK), lib the output path."""
-    objs = []
     odir = os.path.dirname(os.path.abspath(lib))
+    cmds, objs = [], []
     for src in SOURCES:
         obj = os.path.join(odir, src + ".o")
         lang = [] if src.endswith(".hip") else ["-x", "hip"]
-        cmd = ([HIPCC] + COMMON + ["-D" + d for d in defines] + lang
-               + ["-c", os.path.join(CSRC, src), "-o", obj])
+        cmds.append([HIPCC] + COMMON + ["-D" + d for d in defines] + lang
+                    + ["-c", os.path.join(CSRC, src), "-o", obj])
+        objs.append(obj)
+    # translation units compile in parallel (the kernels' unit dominates)
+    procs = []
+    for cmd in cmds:
         if verbose:
             print(" ".join(cmd), flush=True)
-        subprocess.run(cmd, check=True)
-        objs.append(obj)
+        procs.append(subprocess.Popen(cmd))
+    failed = [c for c, p in zip(cmds, procs) if p.wait() != 0]
+    if failed:
+        raise subprocess.CalledProcessError(1, failed[0])
     cmd = [HIPCC, "--offload-arch=gfx950", "-shared", "-fPIC"] + objs + ["-o", lib + ".tmp"]
     if verbose:
         print(" ".join(cmd), flush=True)

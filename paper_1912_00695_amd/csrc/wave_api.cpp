@@ -14,6 +14,7 @@
 #include "../../include/wave.h"
 #include "wave_host.h"
 #include "wave_internal.h"
+#include "wave_launch.h"
 
 namespace wave {
 
@@ -52,8 +53,9 @@ bool grid_ok(const wave_grid* g) {
   if (st != WAVE_STORE_F32 && st != WAVE_STORE_F16 && st != WAVE_STORE_BF16) return false;
   if (st == WAVE_STORE_F32 && (g->storage & WAVE_STORE_DIFF)) return false;
   if (g->path & ~(WAVE_PATH_ONE_STEP | WAVE_PATH_TWO_STEP | WAVE_PATH_STREAM |
-                  WAVE_PATH_CACHED | WAVE_PATH_LINEAR))
+                  WAVE_PATH_CACHED | WAVE_PATH_LINEAR | WAVE_PATH_GRAPH | WAVE_PATH_DIRECT))
     return false;
+  if ((g->path & WAVE_PATH_GRAPH) && (g->path & WAVE_PATH_DIRECT)) return false;
   if ((g->path & WAVE_PATH_ONE_STEP) && (g->path & WAVE_PATH_TWO_STEP)) return false;
   if ((g->path & WAVE_PATH_STREAM) && (g->path & WAVE_PATH_CACHED)) return false;
   if (g->zchunk < 0 || g->zchunk > MAXZCHUNK) return false;
@@ -120,7 +122,8 @@ int64_t max_tiles(const Geom& G) {
 int store_kind(const wave_grid* g) { return g->storage & ~WAVE_STORE_DIFF; }
 bool store_diff(const wave_grid* g) { return (g->storage & WAVE_STORE_DIFF) != 0; }
 
-Layout make_layout(const wave_grid* g, int nsrc, int nrec, int mode, int ckpt_every) {
+Layout make_layout(const wave_grid* g, int nsrc, int nrec, int mode, int ckpt_every,
+                   bool fused_levels) {
   const Geom G = make_geom(g);
   Layout L{};
   size_t off = 0;
@@ -149,7 +152,8 @@ Layout make_layout(const wave_grid* g, int nsrc, int nrec, int mode, int ckpt_ev
     L.pts[s].samp_idx = take(n8 * sizeof(int));
     L.pts[s].samp_w = take(n8 * sizeof(float));
   }
-  L.fused = mode == WAVE_MODE_FORWARD && store_kind(g) == WAVE_STORE_F32 && g->so / 2 <= 4;
+  L.fused = fused_levels && mode == WAVE_MODE_FORWARD && store_kind(g) == WAVE_STORE_F32 &&
+            g->so / 2 <= 4;
   if (L.fused) {
     // each corner of a source lies in the extended region of at most 2 tiles per
     // axis (x extension 4 < TX, y extension r <= 4 < TY, z extension r <= 4 <= half
@@ -501,8 +505,8 @@ StagingPool& staging() {
   return *pool;
 }
 
-void Blob::alloc(size_t n) {
-  bytes = staging().take(n);
+void Blob::alloc(size_t n, bool want_pinned) {
+  bytes = want_pinned ? staging().take(n) : nullptr;
   pinned = bytes != nullptr;
   if (!pinned) bytes = new char[n];
 }
@@ -527,16 +531,17 @@ hipError_t upload_blob(const Blob& b, char* dst, hipStream_t s) {
 }
 
 int init_ctx(Ctx& C, const wave_grid* g, int nsrc, int nrec, int mode, int ckpt_every, void* ws,
-             size_t ws_bytes, void* stream, int zchunk) {
+             size_t ws_bytes, void* stream, int zchunk, bool fused_levels) {
   C.g = g;
   C.G = make_geom(g);
   C.T = make_tiling(C.G, zchunk > 0 ? zchunk : g->zchunk,
                     store_kind(g) != WAVE_STORE_F32 && !store_diff(g));
-  C.L = make_layout(g, nsrc, nrec, mode, ckpt_every);
+  C.L = make_layout(g, nsrc, nrec, mode, ckpt_every, fused_levels);
   if (ws == nullptr || (reinterpret_cast<uintptr_t>(ws) % kAlign) != 0) return WAVE_EINVAL;
   if (ws_bytes < C.L.total) return WAVE_ENOMEM;
   C.ws = static_cast<char*>(ws);
   C.s = static_cast<hipStream_t>(stream);
+  C.path = g->path;
   // Non-temporal hints on the streamed arrays when one step's fields (v^2 dt^2 and
   // the stored levels) exceed the 256 MiB Infinity Cache: measured on MI355X at
   // 512^3 they gain ~10 %; below it the cache serves the next step's reads and the
@@ -566,11 +571,12 @@ int init_ctx(Ctx& C, const wave_grid* g, int nsrc, int nrec, int mode, int ckpt_
 }
 
 // Host image of the tables (sponge profiles, injection and sampling tables).
-Blob* build_blob(const Ctx& C, const double* src, int nsrc, const double* rec, int nrec) {
+Blob* build_blob(const Ctx& C, const double* src, int nsrc, const double* rec, int nrec,
+                 bool pinned) {
   const wave_grid* g = C.g;
   Blob* B = new Blob;
   B->base = C.L.tables_beg;
-  B->alloc(C.L.tables_end - C.L.tables_beg);
+  B->alloc(C.L.tables_end - C.L.tables_beg, pinned);
   float* bx = B->at<float>(C.L.bx);
   sponge_1d(g->nx, g->nbl[0], g->nbl[1], g->hx, g->vmax, g->dt, bx);
   std::fill(bx + g->nx, bx + C.G.pitch, 0.f);  // padding columns
@@ -585,12 +591,14 @@ Blob* build_blob(const Ctx& C, const double* src, int nsrc, const double* rec, i
   return B;
 }
 
+// noalloc: one-step layout and tables staged in ordinary heap memory (no HIP
+// allocation anywhere in the call)
 int setup(Ctx& C, const wave_grid* g, const float* vel, const double* src, int nsrc,
           const double* rec, int nrec, int mode, int ckpt_every, void* ws, size_t ws_bytes,
-          void* stream, int zchunk = 0) {
-  int st = init_ctx(C, g, nsrc, nrec, mode, ckpt_every, ws, ws_bytes, stream, zchunk);
+          void* stream, int zchunk = 0, bool noalloc = false) {
+  int st = init_ctx(C, g, nsrc, nrec, mode, ckpt_every, ws, ws_bytes, stream, zchunk, !noalloc);
   if (st) return st;
-  Blob* B = build_blob(C, src, nsrc, rec, nrec);
+  Blob* B = build_blob(C, src, nsrc, rec, nrec, !noalloc);
   if (upload_blob(*B, C.ws + C.L.tables_beg, C.s) != hipSuccess) {
     delete B;
     return WAVE_EDEVICE;
@@ -683,6 +691,7 @@ int forward_reduced(Ctx& C, const float* wavelet, int nsrc, int nrec, float* rec
   HIP_TRY(launch_encode_initial(u0, um1, U[0], diff ? D : U[1], stk, diff, meta, 0, C.G, C.s));
   StepArgs a = base_args(C);
   const int r = g->so / 2;
+  LaunchList LL;
   for (int n = 0; n < g->nt; ++n) {
     a.level = n;
     a.cur = U[n & 1];
@@ -697,14 +706,14 @@ int forward_reduced(Ctx& C, const float* wavelet, int nsrc, int nrec, float* rec
     }
     set_inj(a, C, 0, nsrc, nsrc > 0 ? wavelet + (int64_t)n * nsrc : nullptr);
     set_samp(a, C, 1, nrec, n >= 1 && nrec > 0 ? rec_out + (int64_t)(n - 1) * nrec : nullptr);
-    HIP_TRY(launch_step(a, r, false, stk, diff, C.nt, C.s));
+    LL.step(a, r, false, stk, diff, C.nt);
   }
   if (nrec > 0 && g->nt > 0) {
     const PointTables& P = C.L.pts[1];
-    HIP_TRY(launch_sample(U[g->nt & 1], stk, meta, g->nt, C.at<int>(P.samp_idx),
-                          C.at<float>(P.samp_w), nrec, rec_out + (int64_t)(g->nt - 1) * nrec,
-                          C.s));
+    LL.sample(U[g->nt & 1], stk, meta, g->nt, C.at<int>(P.samp_idx), C.at<float>(P.samp_w), nrec,
+              rec_out + (int64_t)(g->nt - 1) * nrec);
   }
+  HIP_TRY(LL.run(C.s, C.path));
   if (u_final != nullptr) HIP_TRY(launch_decode(U[g->nt & 1], stk, meta, g->nt, u_final, C.G, C.s));
   return WAVE_OK;
 }
@@ -719,10 +728,11 @@ int forward_fused(Ctx& C, const float* wavelet, int nsrc, int nrec, float* rec_o
   const wave_grid* g = C.g;
   float* X[4] = {C.at<float>(C.L.u[0]), C.at<float>(C.L.u[1]), C.at<float>(C.L.ux[0]),
                  C.at<float>(C.L.ux[1])};
-  HIP_TRY(launch_pack(u0, X[0], C.G, C.s));
-  HIP_TRY(launch_pack(um1, X[1], C.G, C.s));
-  HIP_TRY(launch_pack(nullptr, X[2], C.G, C.s));  // padding columns are never written
-  HIP_TRY(launch_pack(nullptr, X[3], C.G, C.s));
+  LaunchList LL;
+  LL.pack(u0, X[0], C.G);
+  LL.pack(um1, X[1], C.G);
+  LL.pack(nullptr, X[2], C.G);  // padding columns are never written
+  LL.pack(nullptr, X[3], C.G);
   const int r = g->so / 2;
   const PointTables& PR = C.L.pts[1];
   Fused2Args f{};
@@ -744,7 +754,7 @@ int forward_fused(Ctx& C, const float* wavelet, int nsrc, int nrec, float* rec_o
     }
     set_samp(f.a, C, 1, nrec, n >= 2 && nrec > 0 ? rec_out + (int64_t)(n - 1) * nrec : nullptr);
     f.samp_out2 = n >= 2 && nrec > 0 ? rec_out + (int64_t)(n - 2) * nrec : nullptr;
-    HIP_TRY(launch_fused2(f, r, C.nt, C.s));
+    LL.fused2(f, r, C.nt);
     const int oc = cur, op = prv;
     cur = o2;
     prv = o1;
@@ -753,8 +763,8 @@ int forward_fused(Ctx& C, const float* wavelet, int nsrc, int nrec, float* rec_o
   }
   // Levels now: X[cur] = u^n, X[prv] = u^{n-1}.
   if (nrec > 0 && n >= 2)  // d^{n-2}, before a single step overwrites u^{n-1}
-    HIP_TRY(launch_sample(X[prv], ST_F32, LevelMeta{}, 0, C.at<int>(PR.samp_idx),
-                          C.at<float>(PR.samp_w), nrec, rec_out + (int64_t)(n - 2) * nrec, C.s));
+    LL.sample(X[prv], ST_F32, LevelMeta{}, 0, C.at<int>(PR.samp_idx), C.at<float>(PR.samp_w), nrec,
+              rec_out + (int64_t)(n - 2) * nrec);
   int last = cur;
   if (n < g->nt) {
     StepArgs a = base_args(C);
@@ -763,17 +773,17 @@ int forward_fused(Ctx& C, const float* wavelet, int nsrc, int nrec, float* rec_o
     a.out = X[prv];
     set_inj(a, C, 0, nsrc, nsrc > 0 ? wavelet + (int64_t)n * nsrc : nullptr);
     set_samp(a, C, 1, nrec, n >= 1 && nrec > 0 ? rec_out + (int64_t)(n - 1) * nrec : nullptr);
-    HIP_TRY(launch_step(a, r, false, ST_F32, false, C.nt, C.s));
+    LL.step(a, r, false, ST_F32, false, C.nt);
     last = prv;
   } else if (nrec > 0 && n >= 1) {  // d^{n-1} = R u^n (even step count)
-    HIP_TRY(launch_sample(X[cur], ST_F32, LevelMeta{}, 0, C.at<int>(PR.samp_idx),
-                          C.at<float>(PR.samp_w), nrec, rec_out + (int64_t)(n - 1) * nrec, C.s));
+    LL.sample(X[cur], ST_F32, LevelMeta{}, 0, C.at<int>(PR.samp_idx), C.at<float>(PR.samp_w), nrec,
+              rec_out + (int64_t)(n - 1) * nrec);
   }
   if (nrec > 0 && n < g->nt)  // d^{nt-1} = R u^{nt} after the final single step
-    HIP_TRY(launch_sample(X[last], ST_F32, LevelMeta{}, 0, C.at<int>(PR.samp_idx),
-                          C.at<float>(PR.samp_w), nrec, rec_out + (int64_t)(g->nt - 1) * nrec,
-                          C.s));
-  if (u_final != nullptr) HIP_TRY(launch_unpack(X[last], u_final, C.G, C.s));
+    LL.sample(X[last], ST_F32, LevelMeta{}, 0, C.at<int>(PR.samp_idx), C.at<float>(PR.samp_w), nrec,
+              rec_out + (int64_t)(g->nt - 1) * nrec);
+  if (u_final != nullptr) LL.unpack(X[last], u_final, C.G);
+  HIP_TRY(LL.run(C.s, C.path));
   return WAVE_OK;
 }
 
@@ -805,8 +815,9 @@ int forward_impl(const wave_grid* g, const float* vel, const float* wavelet,
   if (fused && fused_tiling_ok(C))
     return forward_fused(C, wavelet, nsrc, nrec, rec_out, u0, um1, u_final);
   float* X[2] = {C.at<float>(C.L.u[0]), C.at<float>(C.L.u[1])};
-  HIP_TRY(launch_pack(u0, X[0], C.G, C.s));
-  HIP_TRY(launch_pack(um1, X[1], C.G, C.s));
+  LaunchList LL;
+  LL.pack(u0, X[0], C.G);
+  LL.pack(um1, X[1], C.G);
   const int64_t N = (int64_t)g->nx * g->ny * g->nz;
   StepArgs a = base_args(C);
   const int r = g->so / 2;
@@ -815,8 +826,8 @@ int forward_impl(const wave_grid* g, const float* vel, const float* wavelet,
     float* prev = X[(n + 1) & 1];
     if (ckpt != nullptr && n % ckpt_every == 0) {
       const int64_t k = n / ckpt_every;
-      HIP_TRY(launch_unpack(cur, ckpt + (2 * k) * N, C.G, C.s));
-      HIP_TRY(launch_unpack(prev, ckpt + (2 * k + 1) * N, C.G, C.s));
+      LL.unpack(cur, ckpt + (2 * k) * N, C.G);
+      LL.unpack(prev, ckpt + (2 * k + 1) * N, C.G);
     }
     a.cur = cur;
     a.prev = prev;
@@ -824,17 +835,17 @@ int forward_impl(const wave_grid* g, const float* vel, const float* wavelet,
     set_inj(a, C, 0, nsrc, nsrc > 0 ? wavelet + (int64_t)n * nsrc : nullptr);
     set_samp(a, C, 1, nrec, n >= 1 && nrec > 0 ? rec_out + (int64_t)(n - 1) * nrec : nullptr);
     if (basic)
-      HIP_TRY(launch_step_basic(a, r, C.s));
+      LL.step_basic(a, r);
     else
-      HIP_TRY(launch_step(a, r, false, ST_F32, false, C.nt, C.s));
+      LL.step(a, r, false, ST_F32, false, C.nt);
   }
   if (nrec > 0 && g->nt > 0) {
     const PointTables& P = C.L.pts[1];
-    HIP_TRY(launch_sample(X[g->nt & 1], ST_F32, LevelMeta{}, g->nt, C.at<int>(P.samp_idx),
-                          C.at<float>(P.samp_w), nrec, rec_out + (int64_t)(g->nt - 1) * nrec,
-                          C.s));
+    LL.sample(X[g->nt & 1], ST_F32, LevelMeta{}, g->nt, C.at<int>(P.samp_idx),
+              C.at<float>(P.samp_w), nrec, rec_out + (int64_t)(g->nt - 1) * nrec);
   }
-  if (u_final != nullptr) HIP_TRY(launch_unpack(X[g->nt & 1], u_final, C.G, C.s));
+  if (u_final != nullptr) LL.unpack(X[g->nt & 1], u_final, C.G);
+  HIP_TRY(LL.run(C.s, C.path));
   return WAVE_OK;
 }
 
@@ -884,7 +895,6 @@ const char* wave_status_string(int status) {
     case WAVE_EDEVICE: return "HIP runtime error";
     case WAVE_EBUSY: return "over the memory budget";
     case WAVE_EAGAIN: return "not ready";
-    case WAVE_ELIMIT: return "larger than the static scratch";
     default: return "unknown status";
   }
 }
@@ -924,8 +934,9 @@ int wave_adjoint(const wave_grid* g, const float* vel, const float* rec_data,
              ws_bytes, hip_stream);
   if (st) return st;
   float* X[2] = {C.at<float>(C.L.u[0]), C.at<float>(C.L.u[1])};
-  HIP_TRY(launch_pack(nullptr, X[0], C.G, C.s));
-  HIP_TRY(launch_pack(nullptr, X[1], C.G, C.s));
+  LaunchList LL;
+  LL.pack(nullptr, X[0], C.G);
+  LL.pack(nullptr, X[1], C.G);
   StepArgs a = base_args(C);
   const int r = g->so / 2;
   const int nt = g->nt;
@@ -936,14 +947,15 @@ int wave_adjoint(const wave_grid* g, const float* vel, const float* rec_data,
     set_inj(a, C, 1, nrec, nrec > 0 ? rec_data + (int64_t)n * nrec : nullptr);
     set_samp(a, C, 0, nsrc,
              (n + 1 <= nt - 1 && nsrc > 0) ? src_out + (int64_t)(n + 1) * nsrc : nullptr);
-    HIP_TRY(launch_step(a, r, false, ST_F32, false, C.nt, C.s));
+    LL.step(a, r, false, ST_F32, false, C.nt);
   }
   if (nsrc > 0 && nt > 0) {
     const PointTables& P = C.L.pts[0];
-    HIP_TRY(launch_sample(X[0], ST_F32, LevelMeta{}, 0, C.at<int>(P.samp_idx),
-                          C.at<float>(P.samp_w), nsrc, src_out, C.s));
+    LL.sample(X[0], ST_F32, LevelMeta{}, 0, C.at<int>(P.samp_idx), C.at<float>(P.samp_w), nsrc,
+              src_out);
   }
-  if (lam_final != nullptr) HIP_TRY(launch_unpack(X[0], lam_final, C.G, C.s));
+  if (lam_final != nullptr) LL.unpack(X[0], lam_final, C.G);
+  HIP_TRY(LL.run(C.s, C.path));
   return WAVE_OK;
 }
 
@@ -978,38 +990,39 @@ int backward_accumulate(const wave_grid* g, const float* vel, const float* wavel
   float* lam[2] = {C.at<float>(C.L.lam[0]), C.at<float>(C.L.lam[1])};
   float* seg = C.at<float>(C.L.seg);
   float* ick = C.at<float>(C.L.ick);
-  HIP_TRY(launch_pack(nullptr, graw, C.G, C.s));
-  HIP_TRY(launch_pack(nullptr, lam[0], C.G, C.s));
-  HIP_TRY(launch_pack(nullptr, lam[1], C.G, C.s));
+  LaunchList LL;
+  LL.pack(nullptr, graw, C.G);
+  LL.pack(nullptr, lam[0], C.G);
+  LL.pack(nullptr, lam[1], C.G);
   StepArgs a = base_args(C);
   if (ckpt == nullptr) {
     // internal forward pass keeping (u^{kC}, u^{kC-1}) pitched in the workspace
     float* X[2] = {C.at<float>(C.L.u[0]), C.at<float>(C.L.u[1])};
-    HIP_TRY(launch_pack(nullptr, X[0], C.G, C.s));
-    HIP_TRY(launch_pack(nullptr, X[1], C.G, C.s));
+    LL.pack(nullptr, X[0], C.G);
+    LL.pack(nullptr, X[1], C.G);
     set_samp(a, C, 1, 0, nullptr);
     for (int n = 0; n < nt; ++n) {
       float* cur = X[n & 1];
       float* prev = X[(n + 1) & 1];
       if (n % Cs == 0) {
         const int64_t k = n / Cs;
-        HIP_TRY(launch_copy(cur, ick + (2 * k) * F, F, C.s));
-        HIP_TRY(launch_copy(prev, ick + (2 * k + 1) * F, F, C.s));
+        LL.copy(cur, ick + (2 * k) * F, F);
+        LL.copy(prev, ick + (2 * k + 1) * F, F);
       }
       a.cur = cur; a.prev = prev; a.out = prev;
       set_inj(a, C, 0, nsrc, nsrc > 0 ? wavelet + (int64_t)n * nsrc : nullptr);
-      HIP_TRY(launch_step(a, r, false, ST_F32, false, C.nt, C.s));
+      LL.step(a, r, false, ST_F32, false, C.nt);
     }
   }
   for (int s = C.L.nseg - 1; s >= 0; --s) {
     const int n0 = s * Cs, n1 = std::min(n0 + Cs, nt);
     // seg slot m holds u^{n0-1+m}
     if (ckpt != nullptr) {
-      HIP_TRY(launch_pack(ckpt + (2 * (int64_t)s) * N, seg + 1 * F, C.G, C.s));
-      HIP_TRY(launch_pack(ckpt + (2 * (int64_t)s + 1) * N, seg + 0 * F, C.G, C.s));
+      LL.pack(ckpt + (2 * (int64_t)s) * N, seg + 1 * F, C.G);
+      LL.pack(ckpt + (2 * (int64_t)s + 1) * N, seg + 0 * F, C.G);
     } else {
-      HIP_TRY(launch_copy(ick + (2 * (int64_t)s) * F, seg + 1 * F, F, C.s));
-      HIP_TRY(launch_copy(ick + (2 * (int64_t)s + 1) * F, seg + 0 * F, F, C.s));
+      LL.copy(ick + (2 * (int64_t)s) * F, seg + 1 * F, F);
+      LL.copy(ick + (2 * (int64_t)s + 1) * F, seg + 0 * F, F);
     }
     set_samp(a, C, 1, 0, nullptr);
     a.ufwd = nullptr;
@@ -1019,7 +1032,7 @@ int backward_accumulate(const wave_grid* g, const float* vel, const float* wavel
       a.prev = seg + (int64_t)(n - n0) * F;
       a.out = seg + (int64_t)(n - n0 + 2) * F;
       set_inj(a, C, 0, nsrc, nsrc > 0 ? wavelet + (int64_t)n * nsrc : nullptr);
-      HIP_TRY(launch_step(a, r, false, ST_F32, false, C.nt, C.s));
+      LL.step(a, r, false, ST_F32, false, C.nt);
     }
     for (int n = n1 - 1; n >= n0; --n) {
       a.cur = lam[(n + 1) & 1];
@@ -1033,17 +1046,17 @@ int backward_accumulate(const wave_grid* g, const float* vel, const float* wavel
                (grad_wavelet != nullptr && nsrc > 0 && n + 1 <= nt - 1)
                    ? grad_wavelet + (int64_t)(n + 1) * nsrc
                    : nullptr);
-      HIP_TRY(launch_step(a, r, true, ST_F32, false, false, C.s));
+      LL.step(a, r, true, ST_F32, false, false);
     }
   }
   if (grad_wavelet != nullptr && nsrc > 0 && nt > 0) {
     const PointTables& P = C.L.pts[0];
-    HIP_TRY(launch_sample(lam[0], ST_F32, LevelMeta{}, 0, C.at<int>(P.samp_idx),
-                          C.at<float>(P.samp_w), nsrc, grad_wavelet, C.s));
+    LL.sample(lam[0], ST_F32, LevelMeta{}, 0, C.at<int>(P.samp_idx), C.at<float>(P.samp_w), nsrc,
+              grad_wavelet);
   }
-  if (image) {
-    HIP_TRY(launch_unpack(graw, out, C.G, C.s));
-  } else {
+  if (image) LL.unpack(graw, out, C.G);
+  HIP_TRY(LL.run(C.s, C.path));
+  if (!image) {
     // dL/dm = -graw / dt^2  ->  dL/dv = -2 v^-3 dL/dm = (2 / dt^2) graw / v^3
     HIP_TRY(launch_grad_finalize(graw, vel, grad_vel, C.G, 2.0 / (g->dt * g->dt), C.s));
   }

@@ -84,7 +84,7 @@ struct Shot {
 };
 
 size_t shot_bytes(const wave_grid* g, int nsrc, int nrec) {
-  const Layout L = make_layout(g, nsrc, nrec, WAVE_MODE_FORWARD, 0);
+  const Layout L = make_layout(g, nsrc, nrec, WAVE_MODE_FORWARD, 0, false);
   return L.total + align_up((size_t)g->nt * nsrc * sizeof(float)) +
          align_up((size_t)g->nt * nrec * sizeof(float));
 }
@@ -246,6 +246,7 @@ class Engine {
   void loop() {
     (void)hipSetDevice(device_);
     std::vector<Shot*> resident;  // UPLOADING or ACTIVE, worker-owned view
+    std::vector<Shot*> finished;  // done, slot and pool space not yet released
     bool dirty = true;
     double busy_t0 = 0;
     while (true) {
@@ -254,6 +255,13 @@ class Engine {
         std::unique_lock<std::mutex> lk(mu_);
         if (stop_) break;
         if (resident.empty() && queue_.empty()) {
+          if (!finished.empty()) {
+            lk.unlock();
+            for (Shot* s : finished) release(s);
+            finished.clear();
+            dirty = true;
+            continue;
+          }
           cv_.wait_for(lk, std::chrono::milliseconds(2));
           continue;
         }
@@ -297,7 +305,7 @@ class Engine {
           if (s->state != FAILED) keep.push_back(s);
         resident.swap(keep);
       }
-      // promote finished uploads
+      // promote finished uploads (the graph is rebuilt: finished shots leave it)
       for (Shot* s : resident)
         if (s->state.load(std::memory_order_acquire) == UPLOADING &&
             hipEventQuery(s->ready) == hipSuccess) {
@@ -306,6 +314,10 @@ class Engine {
           std::vector<float>().swap(s->vel);
           dirty = true;
         }
+      if (dirty && !finished.empty()) {
+        for (Shot* s : finished) release(s);
+        finished.clear();
+      }
       std::vector<Shot*> active;
       for (Shot* s : resident)
         if (s->state == ACTIVE) active.push_back(s);
@@ -340,18 +352,32 @@ class Engine {
         continue;
       }
       ++replays_;
-      // retire
+      // Finished shots complete at once (traces copied back, latency recorded); their
+      // slots and pool space stay reserved, and their table entries in the graph
+      // (which do nothing past nt), until the graph is rebuilt anyway (new shots
+      // active) or a queued request or an idle engine needs them back.
       std::vector<Shot*> keep;
       for (size_t i = 0; i < active.size(); ++i) active[i]->counter = h_counts_[i];
       for (Shot* s : resident) {
         if (s->state == ACTIVE && s->counter > s->g.nt) {
-          retire(s);
-          dirty = true;
+          finish(s);
+          finished.push_back(s);
         } else {
           keep.push_back(s);
         }
       }
       resident.swap(keep);
+      bool any_active = false, waiting = false;
+      for (Shot* s : resident) any_active = any_active || s->state == ACTIVE;
+      {
+        std::lock_guard<std::mutex> lk(mu_);
+        waiting = !queue_.empty();
+      }
+      if (!finished.empty() && (waiting || !any_active)) {
+        for (Shot* s : finished) release(s);
+        finished.clear();
+        dirty = true;
+      }
       if (resident.empty() && busy_t0 > 0) {
         std::lock_guard<std::mutex> lk(mu_);
         busy_s_ += now_s() - busy_t0;
@@ -397,7 +423,7 @@ class Engine {
     // engine tiles every shot with 32-plane z-chunks (fewer priming re-reads than
     // the single-solve policy gives small grids; the values do not depend on it).
     int st = init_ctx(s->C, g, s->nsrc, s->nrec, WAVE_MODE_FORWARD, 0, base, s->bytes, s_up_,
-                      g->zchunk > 0 ? g->zchunk : kEngineZChunk);
+                      g->zchunk > 0 ? g->zchunk : kEngineZChunk, false);
     if (st) return st;
     s->C.g = &s->g;
     s->off_wav = s->C.L.total;
@@ -501,7 +527,8 @@ class Engine {
     return WAVE_OK;
   }
 
-  void retire(Shot* s) {
+  // The shot's traces go back to the caller's buffer and its request completes.
+  void finish(Shot* s) {
     bool ok = true;
     if (s->nrec > 0 && s->rec_out_h != nullptr)
       ok = hipMemcpyAsync(s->rec_out_h, s->desc.traces, sizeof(float) * (size_t)s->g.nt * s->nrec,
@@ -515,16 +542,25 @@ class Engine {
     s->t_done = now_s();
     s->status = ok ? WAVE_OK : WAVE_EDEVICE;
     s->state = ok ? DONE : FAILED;
-    alloc_.release(s->off, s->bytes);
-    pool_used_ -= align_up(s->bytes);
-    slot_used_[s->slot] = 0;
-    --resident_;
     if (ok) {
       lat_.push_back(s->t_done - s->t_submit);
       total_updates_ += (double)s->g.nx * s->g.ny * s->g.nz * s->g.nt;
       last_done_ = s->t_done;
     }
     std::vector<float>().swap(s->wavelet);
+    done_cv_.notify_all();
+  }
+
+  // Slot and pool space of a finished shot become free (the caller rebuilds the
+  // graph before the next replay, so no launch refers to them any more).
+  void release(Shot* s) {
+    std::lock_guard<std::mutex> lk(mu_);
+    if (s->slot < 0) return;
+    alloc_.release(s->off, s->bytes);
+    pool_used_ -= align_up(s->bytes);
+    slot_used_[s->slot] = 0;
+    s->slot = -1;
+    --resident_;
     done_cv_.notify_all();
   }
 

@@ -52,8 +52,9 @@ struct Blob {
   Blob(const Blob&) = delete;
   Blob& operator=(const Blob&) = delete;
   ~Blob();
-  // take n bytes of storage (pinned when possible)
-  void alloc(size_t n);
+  // take n bytes of storage: page-locked from the staging pool when pinned is set
+  // (and the pool can provide it), else ordinary heap memory
+  void alloc(size_t n, bool pinned = true);
   template <class T>
   T* at(size_t off) { return reinterpret_cast<T*>(bytes + (off - base)); }
   void mark(size_t off, size_t n) {
@@ -73,6 +74,7 @@ struct Ctx {
   char* ws;
   hipStream_t s;
   bool nt;  // streamed arrays bypass the caches (working set above the Infinity Cache)
+  int path;  // the grid's WAVE_PATH_* flags
   double wx[MAXR + 1], wy[MAXR + 1], wz[MAXR + 1], wc;
   template <class T>
   T* at(size_t off) const { return reinterpret_cast<T*>(ws + off); }
@@ -90,11 +92,15 @@ bool points_ok(const wave_grid* g, const double* xyz, int np);
 Geom make_geom(const wave_grid* g);
 // zchunk > 0 fixes the z-chunk length; 0 applies the single-solve policy
 Tiling make_tiling(const Geom& G, int zchunk = 0, bool short_chunks = false);
-Layout make_layout(const wave_grid* g, int nsrc, int nrec, int mode, int ckpt_every);
+// fused_levels: an FP32 forward layout at radius <= 4 also holds the two-step
+// kernel's two extra levels and extended-tile tables (false: one-step only)
+Layout make_layout(const wave_grid* g, int nsrc, int nrec, int mode, int ckpt_every,
+                   bool fused_levels = true);
 // geometry, tiling, layout and weights of a call on workspace ws (no device work)
 int init_ctx(Ctx& C, const wave_grid* g, int nsrc, int nrec, int mode, int ckpt_every, void* ws,
-             size_t ws_bytes, void* stream, int zchunk = 0);
-Blob* build_blob(const Ctx& C, const double* src, int nsrc, const double* rec, int nrec);
+             size_t ws_bytes, void* stream, int zchunk = 0, bool fused_levels = true);
+Blob* build_blob(const Ctx& C, const double* src, int nsrc, const double* rec, int nrec,
+                 bool pinned = true);
 StepArgs base_args(const Ctx& C);
 void set_inj(StepArgs& a, const Ctx& C, int set, int np, const float* row);
 void set_samp(StepArgs& a, const Ctx& C, int set, int np, float* row);

@@ -15,16 +15,16 @@ import torch
 HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libwave.so")
 
-OK, EINVAL, ECFL, ENOMEM, EDEVICE, EBUSY, EAGAIN, ELIMIT = 0, -1, -2, -3, -4, -5, -6, -7
+OK, EINVAL, ECFL, ENOMEM, EDEVICE, EBUSY, EAGAIN = 0, -1, -2, -3, -4, -5, -6
 STORE_F32, STORE_F16, STORE_BF16, STORE_DIFF = 0, 1, 2, 16
 MODE_FORWARD, MODE_ADJOINT, MODE_GRADIENT = 0, 1, 2
 # execution-path flags (kernels, launch shapes, cache hints; never the arithmetic)
 PATH_ONE_STEP, PATH_TWO_STEP, PATH_STREAM, PATH_CACHED, PATH_LINEAR = 1, 2, 4, 8, 16
+PATH_GRAPH, PATH_DIRECT = 32, 64
 
 # Entry points declared in include/wave.h.
 SYMBOLS = ["wave_cfl_dt_max", "wave_workspace_bytes", "wave_checkpoint_bytes", "wave_forward",
-           "wave_forward_unfactorised", "wave_adjoint", "wave_gradient", "wave_rtm",
-           "wave_status_string", "wave_version"]
+           "wave_forward_unfactorised", "wave_adjoint", "wave_gradient", "wave_rtm", "wave_status_string", "wave_version"]
 
 
 class WaveError(RuntimeError):
@@ -172,18 +172,19 @@ def _sptr(s):
 
 def forward(grid, vel, wavelet=None, src_xyz=None, rec_xyz=None, u0=None, um1=None,
             want_final=False, ckpt_every=0, workspace=None, stream=None, rec_out=None,
-            unfactorised=False):
+            unfactorised=False, u_final=None):
     """Forward solve. Returns dict(rec=[nt][nrec], u_final=[nz][ny][nx] or None,
     ckpt=[nck][2][nz][ny][nx] or None). unfactorised=True runs the ablation entry
-    point wave_forward_unfactorised (no checkpoints)."""
+    point wave_forward_unfactorised (no checkpoints). rec_out and u_final may be
+    passed in (reused output buffers), which also implies want_final."""
     s = _on(_device_of(vel), stream)
     with torch.cuda.stream(s):
         return _forward(grid, vel, wavelet, src_xyz, rec_xyz, u0, um1, want_final, ckpt_every,
-                        workspace, s, rec_out, unfactorised)
+                        workspace, s, rec_out, unfactorised, u_final)
 
 
 def _forward(grid, vel, wavelet, src_xyz, rec_xyz, u0, um1, want_final, ckpt_every, workspace,
-             s, rec_out, unfactorised):
+             s, rec_out, unfactorised, u_final):
     vel = _dev_f32(vel, grid.shape, "vel")
     dev = vel.device
     src = _host_xyz(src_xyz)
@@ -194,7 +195,8 @@ def _forward(grid, vel, wavelet, src_xyz, rec_xyz, u0, um1, want_final, ckpt_eve
         rec_out = torch.empty((nt, nr), dtype=torch.float32, device=dev)
     u0 = _dev_f32(u0, grid.shape, "u0")
     um1 = _dev_f32(um1, grid.shape, "um1")
-    uf = torch.empty(grid.shape, dtype=torch.float32, device=dev) if want_final else None
+    uf = u_final if u_final is not None else (
+        torch.empty(grid.shape, dtype=torch.float32, device=dev) if want_final else None)
     ck = None
     if ckpt_every > 0:
         nck = (nt + ckpt_every - 1) // ckpt_every

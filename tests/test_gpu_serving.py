@@ -66,6 +66,38 @@ def test_engine_matches_oracle():
         assert rel_l2(o, orec) <= 1e-5
 
 
+def test_engine_full_size_shot_matches_oracle():
+    """One shot of the serving mix at full size (160 x 160 x 320, SO8, 20-cell sponge,
+    layered model, 300 steps, source 20 cells below the receiver line), run on the
+    engine beside two 96^3 shots: traces against the FP64 oracle (rel-L2 <= 1e-5,
+    element-wise <= 1e-4 max|ref|) and bitwise against wave_forward."""
+    import torch
+    from paper_1912_00695_amd import serving, wave
+    rng = np.random.default_rng(21)
+    big = serving.mixed_request(rng, shapes=[(160, 160, 320)], sos=(8,), nt_range=(300, 300),
+                                src_z=40.0)
+    small = [serving.mixed_request(rng, shapes=[(96, 96, 96)], sos=(8,), nt_range=(150, 250),
+                                   src_z=40.0) for _ in range(2)]
+    print("engine full-size shot 160x160x320 SO8 nt=300", flush=True)
+    with _engine(budget=16 << 30) as eng:
+        outs = [eng.submit(r["grid"], r["vel"], r["wavelet"], r["src"], r["rec"])
+                for r in [big] + small]
+        eng.drain(300)
+        assert all(eng.poll(i)[0] == 0 for i, _ in outs)
+    got = outs[0][1]
+    g = big["grid"]
+    og = oracle.Grid((g.nx, g.ny, g.nz), (g.hx, g.hy, g.hz), g.so, g.dt, g.nt,
+                     nbl=tuple(g.nbl), vmax=g.vmax)
+    orec, _, _ = oracle.forward(og, big["vel"], big["wavelet"], big["src"], big["rec"])
+    e, m = rel_l2(got, orec), float(np.abs(got - orec).max() / np.abs(orec).max())
+    print("  traces vs oracle: rel-L2 %.3e max %.3e" % (e, m), flush=True)
+    assert np.abs(orec).max() > 0 and e <= 1e-5 and m <= 1e-4
+    dev = torch.device("cuda:0")
+    f = wave.forward(g, torch.from_numpy(big["vel"]).to(dev),
+                     torch.from_numpy(big["wavelet"]).to(dev), big["src"], big["rec"])["rec"]
+    assert np.array_equal(f.cpu().numpy(), got)
+
+
 def test_budget_pressure_and_rejection():
     from paper_1912_00695_amd import serving, wave
     reqs = _small_mix(seed=7, count=6)
