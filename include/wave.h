@@ -65,6 +65,7 @@ extern "C" {
 #define WAVE_EDEVICE (-4) /* a HIP runtime call failed                                      */
 #define WAVE_EBUSY (-5)   /* serving engine: request exceeds the memory budget              */
 #define WAVE_EAGAIN (-6)  /* serving engine: result not ready yet                           */
+#define WAVE_ELIMIT (-7)  /* problem larger than the static scratch of wave_forward_noalloc */
 
 /* Wavefield storage formats (arithmetic is FP32 in every format). The 16-bit
  * formats store each level as value * 2^e with a power-of-two scale e chosen per
@@ -170,6 +171,28 @@ int wave_forward(const wave_grid* g, const float* vel, const float* wavelet,
                  float* rec_out, const float* u0, const float* um1, float* u_final,
                  float* ckpt, int ckpt_every, void* workspace, size_t ws_bytes,
                  void* hip_stream);
+
+/* For callers that cannot allocate device memory (code under HIP graph capture,
+ * tight serving loops, harnesses that forbid hipMalloc): wave_forward without a
+ * workspace argument. Its workspace is a static device array of the library
+ * (wave_noalloc_limit_bytes(), 64 MiB, one per device, held until the process
+ * ends), so the call makes no hipMalloc/hipFree or other allocating HIP call:
+ * its tables are staged in ordinary host heap memory and uploaded with
+ * asynchronous copies on hip_stream. The caller still passes inputs and outputs.
+ * Runs on the current device, one step per launch (the one-step layout of
+ * wave_forward: v^2 dt^2, the levels and the tables must fit the array, else
+ * WAVE_ELIMIT before anything is enqueued; FP32 storage fits grids up to about
+ * 5.5e6 points, e.g. 160^3). No checkpoints; WAVE_PATH_TWO_STEP gives
+ * WAVE_EINVAL. Every call on a device shares that device's array and leaves its
+ * contents behind (each call re-initialises everything it reads): calls that
+ * overlap on one device race, so order them on one stream. Results are bitwise
+ * those of wave_forward with WAVE_PATH_ONE_STEP. */
+int wave_forward_noalloc(const wave_grid* g, const float* vel, const float* wavelet,
+                         const double* src_xyz_h, int nsrc, const double* rec_xyz_h, int nrec,
+                         float* rec_out, const float* u0, const float* um1, float* u_final,
+                         void* hip_stream);
+/* Size in bytes of the static device array behind wave_forward_noalloc. */
+size_t wave_noalloc_limit_bytes(void);
 
 /* Ablation of the paper's basic-versus-aggressive experiment (Section 4, Tables 2
  * and 3): the forward solve of wave_forward with the update evaluated in the

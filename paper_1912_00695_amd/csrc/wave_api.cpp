@@ -787,12 +787,39 @@ int forward_fused(Ctx& C, const float* wavelet, int nsrc, int nrec, float* rec_o
   return WAVE_OK;
 }
 
+// Static scratch of wave_forward_noalloc: file-scope device memory, one copy per
+// device (held until the process ends), shared by every call on that device.
+// In host code `scratch` only names the symbol; its device address on the
+// current device comes from hipGetSymbolAddress, taken once per device.
+constexpr size_t kScratchBytes = (size_t)64 << 20;
+constexpr int kMaxDevices = 64;
+__device__ __align__(256) char scratch[kScratchBytes];
+
+int scratch_address(void** out) {
+  static std::mutex mu;
+  static void* addr[kMaxDevices] = {};
+  int dev = -1;
+  if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= kMaxDevices) return WAVE_EDEVICE;
+  std::lock_guard<std::mutex> lk(mu);
+  if (addr[dev] == nullptr) {
+    void* p = nullptr;
+    if (hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)) != hipSuccess || p == nullptr)
+      return WAVE_EDEVICE;
+    addr[dev] = p;
+  }
+  *out = addr[dev];
+  return WAVE_OK;
+}
+
 // Forward solve behind wave_forward (basic = false) and the unfactorised ablation
-// (basic = true: FP32 storage, SO 8/12/16/24, one step per launch).
+// (basic = true: FP32 storage, SO 8/12/16/24, one step per launch). noalloc: the
+// workspace is the device's static scratch (one-step layout, tables staged in heap
+// memory); workspace and ws_bytes are ignored.
 int forward_impl(const wave_grid* g, const float* vel, const float* wavelet,
                  const double* src_xyz_h, int nsrc, const double* rec_xyz_h, int nrec,
                  float* rec_out, const float* u0, const float* um1, float* u_final, float* ckpt,
-                 int ckpt_every, void* workspace, size_t ws_bytes, void* hip_stream, bool basic) {
+                 int ckpt_every, void* workspace, size_t ws_bytes, void* hip_stream, bool basic,
+                 bool noalloc = false) {
   int st = validate(g);
   if (st) return st;
   if (vel == nullptr || nsrc < 0 || nrec < 0) return WAVE_EINVAL;
@@ -804,11 +831,19 @@ int forward_impl(const wave_grid* g, const float* vel, const float* wavelet,
   if (basic && (g->storage != WAVE_STORE_F32 ||
                 (g->so != 8 && g->so != 12 && g->so != 16 && g->so != 24)))
     return WAVE_EINVAL;
+  if (noalloc) {
+    if (ckpt != nullptr || (g->path & WAVE_PATH_TWO_STEP)) return WAVE_EINVAL;
+    if (make_layout(g, nsrc, nrec, WAVE_MODE_FORWARD, 0, false).total > kScratchBytes)
+      return WAVE_ELIMIT;
+    st = scratch_address(&workspace);
+    if (st) return st;
+    ws_bytes = kScratchBytes;
+  }
   int fz = 0;
-  const bool fused = !basic && ckpt == nullptr && want_fused(g, &fz);
+  const bool fused = !basic && !noalloc && ckpt == nullptr && want_fused(g, &fz);
   Ctx C;
   st = setup(C, g, vel, src_xyz_h, nsrc, rec_xyz_h, nrec, WAVE_MODE_FORWARD, 0, workspace,
-             ws_bytes, hip_stream, fused ? fz : 0);
+             ws_bytes, hip_stream, fused ? fz : 0, noalloc);
   if (st) return st;
   if (store_kind(g) != WAVE_STORE_F32)
     return forward_reduced(C, wavelet, nsrc, nrec, rec_out, u0, um1, u_final);
@@ -845,7 +880,8 @@ int forward_impl(const wave_grid* g, const float* vel, const float* wavelet,
               C.at<float>(P.samp_w), nrec, rec_out + (int64_t)(g->nt - 1) * nrec);
   }
   if (u_final != nullptr) LL.unpack(X[g->nt & 1], u_final, C.G);
-  HIP_TRY(LL.run(C.s, C.path));
+  // the static-scratch variant never builds graphs (instantiation allocates)
+  HIP_TRY(LL.run(C.s, noalloc ? (C.path | WAVE_PATH_DIRECT) & ~WAVE_PATH_GRAPH : C.path));
   return WAVE_OK;
 }
 
@@ -895,6 +931,7 @@ const char* wave_status_string(int status) {
     case WAVE_EDEVICE: return "HIP runtime error";
     case WAVE_EBUSY: return "over the memory budget";
     case WAVE_EAGAIN: return "not ready";
+    case WAVE_ELIMIT: return "larger than the static scratch";
     default: return "unknown status";
   }
 }
@@ -908,6 +945,16 @@ int wave_forward(const wave_grid* g, const float* vel, const float* wavelet,
   return forward_impl(g, vel, wavelet, src_xyz_h, nsrc, rec_xyz_h, nrec, rec_out, u0, um1,
                       u_final, ckpt, ckpt_every, workspace, ws_bytes, hip_stream, false);
 }
+
+int wave_forward_noalloc(const wave_grid* g, const float* vel, const float* wavelet,
+                         const double* src_xyz_h, int nsrc, const double* rec_xyz_h, int nrec,
+                         float* rec_out, const float* u0, const float* um1, float* u_final,
+                         void* hip_stream) {
+  return forward_impl(g, vel, wavelet, src_xyz_h, nsrc, rec_xyz_h, nrec, rec_out, u0, um1,
+                      u_final, nullptr, 0, nullptr, 0, hip_stream, false, true);
+}
+
+size_t wave_noalloc_limit_bytes(void) { return kScratchBytes; }
 
 int wave_forward_unfactorised(const wave_grid* g, const float* vel, const float* wavelet,
                               const double* src_xyz_h, int nsrc, const double* rec_xyz_h,

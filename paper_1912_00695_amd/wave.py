@@ -15,7 +15,7 @@ import torch
 HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libwave.so")
 
-OK, EINVAL, ECFL, ENOMEM, EDEVICE, EBUSY, EAGAIN = 0, -1, -2, -3, -4, -5, -6
+OK, EINVAL, ECFL, ENOMEM, EDEVICE, EBUSY, EAGAIN, ELIMIT = 0, -1, -2, -3, -4, -5, -6, -7
 STORE_F32, STORE_F16, STORE_BF16, STORE_DIFF = 0, 1, 2, 16
 MODE_FORWARD, MODE_ADJOINT, MODE_GRADIENT = 0, 1, 2
 # execution-path flags (kernels, launch shapes, cache hints; never the arithmetic)
@@ -24,7 +24,8 @@ PATH_GRAPH, PATH_DIRECT = 32, 64
 
 # Entry points declared in include/wave.h.
 SYMBOLS = ["wave_cfl_dt_max", "wave_workspace_bytes", "wave_checkpoint_bytes", "wave_forward",
-           "wave_forward_unfactorised", "wave_adjoint", "wave_gradient", "wave_rtm", "wave_status_string", "wave_version"]
+           "wave_forward_unfactorised", "wave_forward_noalloc", "wave_noalloc_limit_bytes",
+           "wave_adjoint", "wave_gradient", "wave_rtm", "wave_status_string", "wave_version"]
 
 
 class WaveError(RuntimeError):
@@ -72,6 +73,10 @@ def lib():
         L.wave_forward_unfactorised.argtypes = [gp, fp, fp, dp, i, dp, i, fp, fp, fp, fp, vp,
                                                 sz, vp]
         L.wave_forward_unfactorised.restype = i
+        L.wave_forward_noalloc.argtypes = [gp, fp, fp, dp, i, dp, i, fp, fp, fp, fp, vp]
+        L.wave_forward_noalloc.restype = i
+        L.wave_noalloc_limit_bytes.argtypes = []
+        L.wave_noalloc_limit_bytes.restype = sz
         L.wave_adjoint.argtypes = [gp, fp, fp, dp, i, dp, i, fp, fp, vp, sz, vp]
         L.wave_adjoint.restype = i
         L.wave_gradient.argtypes = [gp, fp, fp, dp, i, dp, i, fp, fp, i, fp, fp, vp, sz, vp]
@@ -222,6 +227,38 @@ def _forward(grid, vel, wavelet, src_xyz, rec_xyz, u0, um1, want_final, ckpt_eve
         if st != OK:
             raise WaveError(st, "wave_forward")
     return {"rec": rec_out, "u_final": uf, "ckpt": ck}
+
+
+def forward_noalloc(grid, vel, wavelet=None, src_xyz=None, rec_xyz=None, u0=None, um1=None,
+                    want_final=False, stream=None, rec_out=None, u_final=None):
+    """Forward solve through wave_forward_noalloc: the library's static device array
+    is the workspace (no device allocation inside the call). Outputs (rec_out
+    [nt][nrec], u_final [nz][ny][nx]) may be passed in; otherwise they are
+    allocated here, before the call. Returns dict(rec, u_final)."""
+    s = _on(_device_of(vel), stream)
+    with torch.cuda.stream(s):
+        vel = _dev_f32(vel, grid.shape, "vel")
+        dev = vel.device
+        src = _host_xyz(src_xyz)
+        rec = _host_xyz(rec_xyz)
+        ns, nr, nt = src.shape[0], rec.shape[0], grid.nt
+        wav = _dev_f32(wavelet, (nt, ns), "wavelet") if ns else None
+        if rec_out is None:
+            rec_out = torch.empty((nt, nr), dtype=torch.float32, device=dev)
+        if u_final is None and want_final:
+            u_final = torch.empty(grid.shape, dtype=torch.float32, device=dev)
+        u0 = _dev_f32(u0, grid.shape, "u0")
+        um1 = _dev_f32(um1, grid.shape, "um1")
+        st = lib().wave_forward_noalloc(ctypes.byref(grid), _ptr(vel), _ptr(wav), _hptr(src), ns,
+                                        _hptr(rec), nr, _ptr(rec_out) if nr else None, _ptr(u0),
+                                        _ptr(um1), _ptr(u_final), _sptr(s))
+        if st != OK:
+            raise WaveError(st, "wave_forward_noalloc")
+        return {"rec": rec_out, "u_final": u_final}
+
+
+def noalloc_limit_bytes():
+    return lib().wave_noalloc_limit_bytes()
 
 
 def adjoint(grid, vel, rec_data, rec_xyz, src_xyz, want_final=False, workspace=None,

@@ -31,7 +31,7 @@ def test_library_exports_every_declared_symbol():
 
 def test_status_strings():
     L = wave.lib()
-    for s in (0, -1, -2, -3, -4, -5, -6):
+    for s in (0, -1, -2, -3, -4, -5, -6, -7):
         assert L.wave_status_string(s)
     assert L.wave_version().startswith(b"wave")
 
@@ -170,3 +170,19 @@ def test_no_environment_reads_in_the_library():
     import glob
     for f in glob.glob(os.path.join(ROOT, "paper_1912_00695_amd", "csrc", "*")):
         assert "getenv" not in open(f).read(), f
+
+
+def test_noalloc_limit_checked_before_any_device_call():
+    """wave_forward_noalloc rejects a problem whose one-step layout exceeds its static
+    device array (WAVE_ELIMIT) during validation, before any HIP call: this runs
+    without a GPU."""
+    L = wave.lib()
+    assert L.wave_noalloc_limit_bytes() == 64 << 20
+    big = _grid(n=(256, 256, 256))
+    assert L.wave_forward_noalloc(ctypes.byref(big), FAKE, None, None, 0, None, 0, None, None,
+                                  None, None, None) == wave.ELIMIT
+    assert L.wave_forward_noalloc(ctypes.byref(_grid(so=7)), FAKE, None, None, 0, None, 0, None,
+                                  None, None, None, None) == wave.EINVAL
+    two = _grid(path=wave.PATH_TWO_STEP)
+    assert L.wave_forward_noalloc(ctypes.byref(two), FAKE, None, None, 0, None, 0, None, None,
+                                  None, None, None) == wave.EINVAL
