@@ -2,35 +2,22 @@
 against the FP32 GPU solve.
 
 There is no exact reference for a rounded storage format: these tests state the
-error of each format (printed) and check what must hold -- the difference form
-(u, u - u_prev) beats storing two levels, FP16 beats BF16, FP16 in the difference
-form meets rel-L2 <= 1e-2 on the traces (its final-field error, measured at about
-1.2e-2 on the 160^3 case, is bounded at 2e-2), and the per-level power-of-two scales
-make the result independent of the wavefield's magnitude (exactly for FP16, to
-rounding noise for BF16).
+error of each format (printed) and check what must hold -- FP16 in the difference
+form (u, u - u_prev) meets rel-L2 <= 1e-2 against the FP64 oracle on field and
+traces of the reduced-precision workload (at full size, 512^3 x 1000 steps, and
+scaled to 160^3), the difference form beats storing two levels, FP16 beats BF16,
+and the per-level power-of-two scales make the result independent of the
+wavefield's magnitude (exactly for FP16, to rounding noise for BF16).
 """
+import os
+
 import numpy as np
 import pytest
 
-from helpers import Case, rel_l2
-from paper_1912_00695_amd import inputs
+from helpers import c4_case, rel_l2
 
 pytestmark = pytest.mark.gpu
 FORMATS = {"f16": 1, "bf16": 2, "f16_diff": 1 | 16, "bf16_diff": 2 | 16}
-
-
-def c4_case(n=(512, 512, 512), nt=1000, nbl=40):
-    """SO8, smoothed-random velocity in [1500, 4500] m/s (20-cell correlation,
-    seed 4), 15 Hz Ricker at the centre, dt = 0.5 dt_max(4500), receivers along x
-    through the source plane and at z = 20."""
-    h = (10.0, 10.0, 10.0)
-    vel = inputs.smooth_random_range(n, 1500.0, 4500.0, 20.0, seed=4)
-    c = Case(n, h, 8, nt, vel, 4500.0, nbl=(nbl,) * 6)
-    c.src = inputs.point((n[0] // 2, n[1] // 2, n[2] // 2), h)
-    c.wavelet = inputs.ricker(15.0, c.dt, nt)[:, None]
-    c.rec = np.concatenate([inputs.line_x(n, h, n[1] // 2, n[2] // 2 + 10),
-                            inputs.line_x(n, h, n[1] // 2, 20)])
-    return c
 
 
 def _run(case, storage, scale=1.0):
@@ -44,37 +31,83 @@ def _run(case, storage, scale=1.0):
     return out["rec"].cpu().numpy(), out["u_final"].cpu().numpy()
 
 
-def test_reduced_storage_vs_oracle():
-    case = c4_case(n=(160, 160, 160), nt=1000, nbl=20)
-    print("C4-shaped 160^3 SO8 nt=1000 vs FP64 oracle", flush=True)
+def _errors(case):
     orec, ouf, _ = case.oracle_forward()
     err = {}
-    r32, u32 = _run(case, 0)
-    err["f32"] = (rel_l2(u32, ouf), rel_l2(r32, orec))
-    for name, st in FORMATS.items():
+    for name, st in [("f32", 0)] + list(FORMATS.items()):
         r, u = _run(case, st)
         err[name] = (rel_l2(u, ouf), rel_l2(r, orec))
     for k, (eu, er) in err.items():
         print("%-9s field rel-L2 %.3e  traces rel-L2 %.3e" % (k, eu, er), flush=True)
+    return err
+
+
+def test_reduced_storage_vs_oracle_scaled_workload():
+    """The reduced-precision workload scaled to 160^3 (20-cell sponge) with the same
+    wave travel as a fraction of the grid: the full workload's 1000 steps at 512^3
+    become 312 steps (same dt, same velocities). FP32 storage <= 1e-5; FP16
+    difference form <= 1e-2 on field and traces; the difference form beats the naive
+    form and FP16 beats BF16 in each form."""
+    case = c4_case(n=(160, 160, 160), nt=312, nbl=20)
+    print("C4-shaped 160^3 SO8 nt=312 vs FP64 oracle", flush=True)
+    err = _errors(case)
     assert err["f32"][0] <= 1e-5 and err["f32"][1] <= 1e-5
-    assert err["f16_diff"][0] <= 2e-2 and err["f16_diff"][1] <= 1e-2
+    assert err["f16_diff"][0] <= 1e-2 and err["f16_diff"][1] <= 1e-2
     assert err["f16_diff"][0] <= err["f16"][0] and err["bf16_diff"][0] <= err["bf16"][0]
     assert err["f16"][0] <= err["bf16"][0] and err["f16_diff"][0] <= err["bf16_diff"][0]
 
 
-def test_reduced_storage_full_size_vs_fp32():
-    """C4 at full size (512^3, 1000 steps): each format against the FP32 GPU run."""
-    case = c4_case()
-    print("C4 512^3 SO8 nt=1000", flush=True)
-    r32, u32 = _run(case, 0)
-    assert np.abs(r32).max() > 0
-    for name, st in FORMATS.items():
-        r, u = _run(case, st)
-        eu, er = rel_l2(u, u32), rel_l2(r, r32)
-        print("%-9s vs FP32 GPU: field %.3e traces %.3e" % (name, eu, er), flush=True)
+def test_reduced_storage_vs_oracle_late_coda():
+    """160^3 run for 1000 steps: the wave has left the interior through the sponge and
+    the final field is the small late coda, so the rounding noise accumulated over
+    the run is large relative to it (FP16 difference form: about 1.2e-2 on the final
+    field, stated, not claimed against 1e-2). Checked: FP32 <= 1e-5, the FP16
+    difference form's traces <= 1e-2 (they record the whole run), and the orderings
+    of the formats."""
+    case = c4_case(n=(160, 160, 160), nt=1000, nbl=20)
+    print("C4-shaped 160^3 SO8 nt=1000 vs FP64 oracle", flush=True)
+    err = _errors(case)
+    assert err["f32"][0] <= 1e-5 and err["f32"][1] <= 1e-5
+    assert err["f16_diff"][1] <= 1e-2
+    assert err["f16_diff"][0] <= err["f16"][0] and err["bf16_diff"][0] <= err["bf16"][0]
+    assert err["f16"][0] <= err["bf16"][0] and err["f16_diff"][0] <= err["bf16_diff"][0]
+
+
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden", "c4_reference.npz")
+
+
+def test_full_size_c4_vs_oracle():
+    """The reduced-precision workload at its full size (512^3 SO8, 1000 steps,
+    smoothed-random 1500-4500 m/s, 40-cell sponge) against the FP64 oracle's result,
+    stored by tests/golden/make_c4_reference.py (oracle traces of 256 receivers and
+    u^1000 on a regular 64^3 sub-lattice; the sample's rel-L2 estimates the field's).
+    FP32 storage (the non-temporal path this grid takes): rel-L2 <= 1e-5 and
+    element-wise <= 1e-4 max|ref|; FP16 difference form: <= 1e-2 on field and traces;
+    every format's error against the oracle and against the FP32 run is printed."""
+    ref = np.load(GOLDEN, allow_pickle=False)
+    meta = str(ref["meta"])
+    case = c4_case(rec_stride=4)
+    assert '"nrec": %d' % len(case.rec) in meta and '"nt": %d' % case.nt in meta
+    o, st = 4, 8
+    print("C4 512^3 SO8 nt=1000 against the stored oracle result", flush=True)
+    res = {}
+    for name, storage in [("f32", 0)] + list(FORMATS.items()):
+        r, u = _run(case, storage)
+        smp = u[o::st, o::st, o::st]
+        res[name] = (r, smp)
+        eu, er = rel_l2(smp, ref["sample"]), rel_l2(r, ref["traces"])
+        mx = np.abs(smp.astype(np.float64) - ref["sample"]).max() / np.abs(ref["sample"]).max()
+        line = "%-9s vs oracle: field %.3e traces %.3e max %.3e" % (name, eu, er, mx)
+        if name != "f32":
+            line += " | vs FP32: field %.3e traces %.3e" % (rel_l2(smp, res["f32"][1]),
+                                                          rel_l2(r, res["f32"][0]))
+        print(line, flush=True)
         assert np.isfinite(u).all() and np.isfinite(r).all()
+        if name == "f32":
+            assert eu <= 1e-5 and er <= 1e-5 and mx <= 1e-4
         if name == "f16_diff":
-            assert eu <= 3e-2 and er <= 1e-2
+            assert eu <= 1e-2 and er <= 1e-2
+        del u
 
 
 @pytest.mark.parametrize("fmt", ["f16", "bf16", "f16_diff", "bf16_diff"])
