@@ -12,7 +12,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libwave.so")
 SOURCES = ["wave_kernels.hip", "wave_fused.hip", "wave_api.cpp", "wave_engine.cpp",
-           "wave_launch.cpp"]
+           "wave_launch.cpp", "wave_scratch.cpp"]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 COMMON = ["-O3", "-std=c++17", "-fPIC", "-Wall", "-ffp-contract=fast",

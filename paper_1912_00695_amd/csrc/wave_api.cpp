@@ -787,30 +787,6 @@ int forward_fused(Ctx& C, const float* wavelet, int nsrc, int nrec, float* rec_o
   return WAVE_OK;
 }
 
-// Static scratch of wave_forward_noalloc: file-scope device memory, one copy per
-// device (held until the process ends), shared by every call on that device.
-// In host code `scratch` only names the symbol; its device address on the
-// current device comes from hipGetSymbolAddress, taken once per device.
-constexpr size_t kScratchBytes = (size_t)64 << 20;
-constexpr int kMaxDevices = 64;
-__device__ __align__(256) char scratch[kScratchBytes];
-
-int scratch_address(void** out) {
-  static std::mutex mu;
-  static void* addr[kMaxDevices] = {};
-  int dev = -1;
-  if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= kMaxDevices) return WAVE_EDEVICE;
-  std::lock_guard<std::mutex> lk(mu);
-  if (addr[dev] == nullptr) {
-    void* p = nullptr;
-    if (hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)) != hipSuccess || p == nullptr)
-      return WAVE_EDEVICE;
-    addr[dev] = p;
-  }
-  *out = addr[dev];
-  return WAVE_OK;
-}
-
 // Forward solve behind wave_forward (basic = false) and the unfactorised ablation
 // (basic = true: FP32 storage, SO 8/12/16/24, one step per launch). noalloc: the
 // workspace is the device's static scratch (one-step layout, tables staged in heap

@@ -85,6 +85,11 @@ struct Ctx {
     if ((x) != hipSuccess) return WAVE_EDEVICE; \
   } while (0)
 
+// Static workspace of wave_forward_noalloc (wave_scratch.cpp): its size, and its
+// device address on the current device (WAVE_OK, or WAVE_EDEVICE).
+constexpr size_t kScratchBytes = (size_t)64 << 20;
+int scratch_address(void** out);
+
 size_t align_up(size_t v);
 bool grid_ok(const wave_grid* g);
 int validate(const wave_grid* g);  // grid_ok + stability limit
