@@ -174,6 +174,37 @@ def small_grid_leg(dev, solves=20):
     return res
 
 
+def c1_leg(dev, mode, solves=20):
+    """The plain case alone (64^3 SO4, v = 1500 m/s, Gaussian pulse at rest, no
+    sponge, 100 steps), `solves` repeated solves with direct launches (mode
+    "direct") or graph replay ("graph"), for kernel traces of the launch gaps."""
+    import torch
+    from paper_1912_00695_amd import inputs, wave
+    h, n = (10.0, 10.0, 10.0), (64, 64, 64)
+    path = {"direct": wave.PATH_DIRECT, "graph": wave.PATH_GRAPH}[mode]
+    g = wave.make_grid(n, h, 4, 0.5 * wave.cfl_dt_max(4, 1500.0, h), 100, vmax=1500.0,
+                       path=path)
+    v = torch.from_numpy(inputs.constant(n, 1500.0)).to(dev)
+    u0 = torch.from_numpy(inputs.gaussian_pulse(n, (32, 32, 32), 3.0)).to(dev)
+    ws = torch.empty(wave.workspace_bytes(g, 0, 0), dtype=torch.uint8, device=dev)
+    uf = torch.empty((64, 64, 64), dtype=torch.float32, device=dev)
+    fn = lambda: wave.forward(g, v, None, None, None, u0=u0, um1=u0, workspace=ws, u_final=uf)
+    for _ in range(3):
+        fn()
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(solves):
+        fn()
+    e1.record()
+    torch.cuda.synchronize()
+    el = e0.elapsed_time(e1) / 1000.0
+    res = {"mode": mode, "gpts": round(64 ** 3 * 100 * solves / el / 1e9, 2),
+           "us_per_step": round(el / solves / 100 * 1e6, 3)}
+    log("c1 %s: %s" % (mode, res))
+    return res
+
+
 def reduced_precision_leg(dev):
     """512^3 SO8, smoothed-random 1500-4500 m/s, 15 Hz Ricker at the centre, 1000 steps,
     40-cell sponge, receivers at every 4th point of two lines along x (10 cells below
@@ -464,7 +495,7 @@ def main():
                     help="run only the timed solves (for profiler runs)")
     ap.add_argument("--leg", default="",
                     help="run only this leg after the timed solves and print its JSON "
-                         "(small_grids)")
+                         "(small_grids, c1_direct, c1_graph)")
     ap.add_argument("--with-copy", action="store_true",
                     help="after the timed solves, run a plain 256 MiB device copy three times "
                          "(calibrates profiler byte counters against a known size)")
@@ -530,6 +561,8 @@ def main():
         del x, y
     if args.leg == "small_grids":
         out["small_grids"] = small_grid_leg(dev)
+    elif args.leg in ("c1_direct", "c1_graph"):
+        out["c1"] = c1_leg(dev, args.leg[3:])
     if args.only_timed or args.leg:
         print(json.dumps(out), flush=True)
         return

@@ -75,20 +75,24 @@ Geom make_geom(const wave_grid* g) {
   return G;
 }
 
-// z-chunking: floor(512 / tiles per plane) chunks (at least one, of at least 8
-// planes): about 512 workgroups, two per CU, all resident at once, each sweeping one
-// long chunk. Measured on MI355X at SO8, among the chunk lengths tried: 256^3 best at
-// 32 planes (512 workgroups), 384^3 at 128 (432), 448^3 at 224 (392), 512^3 at 256
-// (512). More workgroups at once (576-1024) lost 5-15 %, several rounds of short
-// chunks (the previous policy for large grids: 20 planes) lost 3-6 % at SO8, fewer
-// than ~400 workgroups leave CUs idle. Long chunks also amortise the 2r planes each
-// chunk re-reads to prime its z queue, so the gain grows with the order (512^3 over
+// z-chunking: floor(512 / tiles per plane) chunks (at least one): about 512
+// workgroups, two per CU, all resident at once, each sweeping one long chunk.
+// Measured on MI355X at SO8, among the chunk lengths tried: 256^3 best at 32 planes
+// (512 workgroups), 384^3 at 128 (432), 448^3 at 224 (392), 512^3 at 256 (512). More
+// workgroups at once (576-1024) lost 5-15 %, several rounds of short chunks (the
+// previous policy for large grids: 20 planes) lost 3-6 % at SO8, fewer than ~400
+// workgroups leave CUs idle. Long chunks also amortise the 2r planes each chunk
+// re-reads to prime its z queue, so the gain grows with the order (512^3 over
 // 20-plane chunks: +5 % SO8, +11 % SO16, +23 % SO24; FP32 and the 16-bit difference
-// form). The naive 16-bit form (short_chunks) keeps chunks of 8..32 planes for about
-// 512 workgroups, and balanced chunks of about 20 planes, swept in several rounds,
-// for grids that would need more than 1024 workgroups at 32 planes: 546 Gpt/s at
-// 512^3 SO8 against 498 with one long chunk per workgroup. A positive zchunk fixes
-// the chunk length (the grid's zchunk, or the caller's policy).
+// form). Small grids get short chunks from the same rule (64^3: 1 plane, 256
+// workgroups; 128^3: 4 planes): there a step takes a few microseconds and the
+// workgroup count sets it (64^3 SO4 with graph replay: 4.5 us per step at 1-plane
+// chunks against 8.5 at 8-plane chunks; 128^3 SO4: 7.5 against 9.0). The naive
+// 16-bit form (short_chunks) keeps chunks of 8..32 planes for about 512 workgroups,
+// and balanced chunks of about 20 planes, swept in several rounds, for grids that
+// would need more than 1024 workgroups at 32 planes: 546 Gpt/s at 512^3 SO8 against
+// 498 with one long chunk per workgroup. A positive zchunk fixes the chunk length
+// (the grid's zchunk, or the caller's policy).
 Tiling make_tiling(const Geom& G, int zchunk, bool short_chunks) {
   Tiling T;
   T.ntile_x = (G.nx + TX - 1) / TX;
@@ -104,7 +108,7 @@ Tiling make_tiling(const Geom& G, int zchunk, bool short_chunks) {
     }
   } else if (zc <= 0) {
     const int nch = std::max(1, 512 / bxy);
-    zc = std::max((G.nz + nch - 1) / nch, 8);
+    zc = (G.nz + nch - 1) / nch;
   }
   zc = std::max(1, std::min({zc, G.nz, MAXZCHUNK}));
   T.zchunk = zc;

@@ -211,7 +211,10 @@ static void test_tiling() {
   CHECK(zc(320, false).zchunk == 64 && zc(320, false).nblocks == 500);
   CHECK(zc(384, false).zchunk == 128 && zc(384, false).nblocks == 432);
   CHECK(zc(512, false).zchunk == 256 && zc(512, false).nblocks == 512);
-  CHECK(zc(64, false).zchunk == 8);  // at least 8 planes
+  // small grids: short chunks from the same rule (64^3: 4 tiles per plane, 1-plane
+  // chunks, 256 workgroups; 128^3: 16 tiles, 4 planes, 512 workgroups)
+  CHECK(zc(64, false).zchunk == 1 && zc(64, false).nblocks == 256);
+  CHECK(zc(128, false).zchunk == 4 && zc(128, false).nblocks == 512);
   // naive 16-bit storage: chunks of at most 32 planes, ~20 for large grids
   CHECK(zc(256, true).zchunk == 32);
   CHECK(zc(512, true).zchunk == 20);

@@ -226,8 +226,8 @@ def _with_nt(case, nt):
 
 @pytest.mark.parametrize("so", [2, 4, 6, 8, 10, 12, 14, 16, 24])
 def test_chunk_lengths_give_identical_results(so):
-    """z-chunks of 1, 2, 5 and 23 planes (the whole grid) against the default
-    chunking (8 planes on this 97 x 37 x 23 grid): every point's update reads the
+    """z-chunks of 2, 5, 8 and 23 planes (the whole grid) against the default
+    chunking (1 plane on this 97 x 37 x 23 grid): every point's update reads the
     same values in the same order whatever the chunk (queue priming, the halo loads
     and the LDS ring that holds them only change when values are fetched), so traces
     and final field are bitwise equal; the default run is also checked against the
@@ -238,7 +238,7 @@ def test_chunk_lengths_give_identical_results(so):
     ref = _run(case)
     rec, uf, _ = case.oracle_forward()
     assert rel_l2(ref["u_final"], uf) <= TOL and rel_l2(ref["rec"], rec) <= TOL
-    for zc in (1, 2, 5, 23):
+    for zc in (2, 5, 8, 23):
         g = _run(case, zchunk=zc)
         print("  zchunk", zc, "field equal", np.array_equal(g["u_final"], ref["u_final"]),
               flush=True)
