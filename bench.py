@@ -205,6 +205,17 @@ def c1_leg(dev, mode, solves=20):
     return res
 
 
+_C4_VEL = {}
+
+
+def _c4_velocity():
+    """The 512^3 smoothed-random 1500-4500 m/s model (seed 4), generated once."""
+    from paper_1912_00695_amd import inputs
+    if "v" not in _C4_VEL:
+        _C4_VEL["v"] = inputs.smooth_random_range((512, 512, 512), 1500.0, 4500.0, 20.0, seed=4)
+    return _C4_VEL["v"]
+
+
 def reduced_precision_leg(dev):
     """512^3 SO8, smoothed-random 1500-4500 m/s, 15 Hz Ricker at the centre, 1000 steps,
     40-cell sponge, receivers at every 4th point of two lines along x (10 cells below
@@ -218,7 +229,7 @@ def reduced_precision_leg(dev):
     n, h, nt = (512, 512, 512), (10.0, 10.0, 10.0), 1000
     vmax = 4500.0
     dt = 0.5 * wave.cfl_dt_max(8, vmax, h)
-    vel = torch.from_numpy(inputs.smooth_random_range(n, 1500.0, 4500.0, 20.0, seed=4)).to(dev)
+    vel = torch.from_numpy(_c4_velocity()).to(dev)
     wav = torch.from_numpy(inputs.ricker(15.0, dt, nt)[:, None]).to(dev)
     src = inputs.point((256, 256, 256), h)
     rec = np.concatenate([inputs.line_x(n, h, 256, 266)[::4], inputs.line_x(n, h, 256, 20)[::4]])
@@ -373,15 +384,45 @@ def adjoint_gradient_leg(dev):
     return res
 
 
-def serving_leg(dev, nreq):
-    """The serving workload: Poisson arrivals at 20/s (seed 5) of forward shots drawn
-    from {96^3, 128^3, 192^3, 256^3, 160x160x320} x SO {4, 8} x nt in [200, 1000],
-    layered 1500-4500 m/s models, 20-cell sponge, receiver line at z = 20; then the
-    first 40 of the same requests submitted at once (saturated engine) and solved one
-    by one with wave_forward, for the batched-vs-plain throughput."""
+def serving_saturated_leg(dev, count=40):
+    """The first `count` requests of a seeded serving mix submitted at once (saturated
+    engine), against the same shots solved one by one with wave_forward."""
     import numpy as np
     import torch
     from paper_1912_00695_amd import serving, wave
+    rng = np.random.default_rng(6)
+    reqs = [serving.mixed_request(rng) for _ in range(count)]
+    upd = sum(r["updates"] for r in reqs)
+    with serving.Engine(96 << 30, 64) as eng:
+        t0 = time.perf_counter()
+        for r in reqs:
+            eng.submit(r["grid"], r["vel"], r["wavelet"], r["src"], r["rec"])
+        eng.drain(900)
+        t_batched = time.perf_counter() - t0
+        st = eng.stats()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for r in reqs:
+        wave.forward(r["grid"], torch.from_numpy(r["vel"]).to(dev),
+                     torch.from_numpy(r["wavelet"]).to(dev), r["src"], r["rec"])["rec"].cpu()
+    torch.cuda.synchronize()
+    t_plain = time.perf_counter() - t0
+    res = {"requests": count, "batched_gpts": round(upd / t_batched / 1e9, 2),
+           "plain_sequential_gpts": round(upd / t_plain / 1e9, 2),
+           "speedup": round(t_plain / t_batched, 3), "graph_builds": st["graph_builds"],
+           "note": "same requests, bitwise-identical results; both include host->device "
+                   "upload of each request's inputs"}
+    log("serving saturated: %s" % res)
+    return res
+
+
+def serving_leg(dev, nreq):
+    """The serving workload: Poisson arrivals at 20/s (seed 5) of forward shots drawn
+    from {96^3, 128^3, 192^3, 256^3, 160x160x320} x SO {4, 8} x nt in [200, 1000],
+    layered 1500-4500 m/s models, 20-cell sponge, receiver line at z = 20; then 40
+    requests of the same mix (seed 6) submitted at once (saturated engine) and solved
+    one by one with wave_forward, for the batched-vs-plain throughput."""
+    from paper_1912_00695_amd import serving
     res = {}
     with serving.Engine(96 << 30, 64) as eng:
         st, recs = serving.run_poisson(eng, nreq, 20.0, seed=5, log=log)
@@ -396,50 +437,36 @@ def serving_leg(dev, nreq):
                       "busy_gpts": round(st["total_gpt"] / max(st["busy_s"], 1e-9), 2),
                       "max_resident": st["max_resident"], "graph_builds": st["graph_builds"]}
     log("serving poisson: %s" % res["poisson"])
-    rng = np.random.default_rng(6)
-    reqs = [serving.mixed_request(rng) for _ in range(40)]
-    upd = sum(r["updates"] for r in reqs)
-    with serving.Engine(96 << 30, 64) as eng:
-        t0 = time.perf_counter()
-        for r in reqs:
-            eng.submit(r["grid"], r["vel"], r["wavelet"], r["src"], r["rec"])
-        eng.drain(900)
-        t_batched = time.perf_counter() - t0
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    for r in reqs:
-        wave.forward(r["grid"], torch.from_numpy(r["vel"]).to(dev),
-                     torch.from_numpy(r["wavelet"]).to(dev), r["src"], r["rec"])["rec"].cpu()
-    torch.cuda.synchronize()
-    t_plain = time.perf_counter() - t0
-    res["saturated_40"] = {"batched_gpts": round(upd / t_batched / 1e9, 2),
-                           "plain_sequential_gpts": round(upd / t_plain / 1e9, 2),
-                           "speedup": round(t_plain / t_batched, 3),
-                           "note": "same requests, bitwise-identical results; both include "
-                                   "host->device upload of each request's inputs"}
-    log("serving saturated: %s" % res["saturated_40"])
+    res["saturated_40"] = serving_saturated_leg(dev)
     return res
 
 
-def cpu_baseline(P, target_s=20.0):
-    """The FP64 oracle on the host cores, on a bounded number of time steps of the
-    same 256^3 SO8 workload."""
+def _oracle_sample(P, target_s, est_steps=6):
+    """Time the FP64 oracle on the first steps of workload P: a 2-step run (thread
+    start-up, first touch), an est_steps run for the time per step, then as many
+    steps as fit target_s. Returns (Gpt-updates/s, steps, seconds)."""
     import numpy as np
     import oracle
-    # a 2-step run first (thread start-up and first touch of the arrays), then a
-    # 6-step run to estimate the time per step, then the timed sample
     og = oracle.Grid(P["n"], P["h"], P["so"], P["dt"], 2, nbl=P["nbl"], vmax=P["vmax"])
     oracle.forward(og, P["vel"], P["wav"][:2], P["src"], P["rec"])
-    og = og.replace(nt=6)
+    og = og.replace(nt=est_steps)
     t0 = time.perf_counter()
-    oracle.forward(og, P["vel"], P["wav"][:6], P["src"], P["rec"])
-    per_step = (time.perf_counter() - t0) / 6
+    oracle.forward(og, P["vel"], P["wav"][:est_steps], P["src"], P["rec"])
+    per_step = (time.perf_counter() - t0) / est_steps
     nsteps = int(max(2, min(P["nt"], target_s / max(per_step, 1e-6))))
     og = og.replace(nt=nsteps)
     t0 = time.perf_counter()
     oracle.forward(og, P["vel"], P["wav"][:nsteps], P["src"], P["rec"])
     el = time.perf_counter() - t0
-    npts = int(np.prod(P["n"]))
+    return int(np.prod(P["n"])) * nsteps / el / 1e9, nsteps, el
+
+
+def cpu_baseline(P, target_s=15.0):
+    """The FP64 oracle on the host cores, on bounded samples (the first time steps)
+    of the benchmark workload (256^3 SO8), of the same at SO4, and of the 512^3 SO8
+    reduced-precision workload; and on one thread for the plain 64^3 case."""
+    import oracle
+    val, nsteps, el = _oracle_sample(P, target_s)
     cpu = "unknown"
     try:
         for line in open("/proc/cpuinfo"):
@@ -448,13 +475,24 @@ def cpu_baseline(P, target_s=20.0):
                 break
     except OSError:
         pass
-    res = {"value": npts * nsteps / el / 1e9, "unit": "Gpt-updates/s",
+    res = {"value": val, "unit": "Gpt-updates/s",
            "cores": oracle.num_threads(), "kind": "oracle", "cpu_model": cpu,
            "sample": "FP64 oracle, 256^3 SO8 two-layer + 40-cell sponge, source and 256 "
                      "receivers, first %d of the 500 time steps (%.1f s)" % (nsteps, el)}
+    v4, n4, e4 = _oracle_sample(c2_problem(4), 8.0)
+    res["c2_256cube_so4"] = {"value": round(v4, 4), "unit": "Gpt-updates/s",
+                             "sample": "first %d of 500 steps (%.1f s)" % (n4, e4)}
+    from paper_1912_00695_amd import inputs
+    n5, h5 = (512, 512, 512), (10.0, 10.0, 10.0)
+    dt5 = 0.5 * oracle.cfl_dt_max(8, 4500.0, h5)
+    P5 = dict(n=n5, h=h5, so=8, dt=dt5, nt=1000, nbl=(40,) * 6, vmax=4500.0,
+              vel=_c4_velocity(), wav=inputs.ricker(15.0, dt5, 1000)[:, None],
+              src=inputs.point((256, 256, 256), h5), rec=inputs.line_x(n5, h5, 256, 266))
+    v5, n5s, e5 = _oracle_sample(P5, 8.0, est_steps=2)
+    res["c4_512cube_so8"] = {"value": round(v5, 4), "unit": "Gpt-updates/s",
+                             "sample": "first %d of 1000 steps (%.1f s)" % (n5s, e5)}
     # one thread on the small plain case: 64^3 SO4, homogeneous 1500 m/s, Gaussian
     # pulse at rest at the centre, 100 steps
-    from paper_1912_00695_amd import inputs
     n1, h1 = (64, 64, 64), (10.0, 10.0, 10.0)
     v1 = inputs.constant(n1, 1500.0)
     g1 = oracle.Grid(n1, h1, 4, 0.5 * oracle.cfl_dt_max(4, 1500.0, h1), 100, vmax=1500.0)
@@ -495,7 +533,8 @@ def main():
                     help="run only the timed solves (for profiler runs)")
     ap.add_argument("--leg", default="",
                     help="run only this leg after the timed solves and print its JSON "
-                         "(small_grids, c1_direct, c1_graph)")
+                         "(small_grids, c1_direct, c1_graph, adjoint_gradient, "
+                         "serving_saturated, serving)")
     ap.add_argument("--with-copy", action="store_true",
                     help="after the timed solves, run a plain 256 MiB device copy three times "
                          "(calibrates profiler byte counters against a known size)")
@@ -563,6 +602,12 @@ def main():
         out["small_grids"] = small_grid_leg(dev)
     elif args.leg in ("c1_direct", "c1_graph"):
         out["c1"] = c1_leg(dev, args.leg[3:])
+    elif args.leg == "adjoint_gradient":
+        out["adjoint_gradient_c3"] = adjoint_gradient_leg(dev)
+    elif args.leg == "serving_saturated":
+        out["serving_saturated"] = serving_saturated_leg(dev)
+    elif args.leg == "serving":
+        out["serving"] = serving_leg(dev, args.serving_requests)
     if args.only_timed or args.leg:
         print(json.dumps(out), flush=True)
         return

@@ -341,11 +341,13 @@ class Engine {
       const int reps = std::max(1, std::min(64, (int)(kSyncWork / (kReplaySteps * step_s))));
       bool launched = true;
       for (int k = 0; k < reps && launched; ++k) launched = hipGraphLaunch(gexec_, s_exec_) == hipSuccess;
+      // counters of the shots in the graph, in the slot order the last rebuild uploaded
+      // (the active set can shrink between rebuilds: finished shots stay in the graph)
+      const int ng = (int)graph_shots_.size();
       if (!launched ||
-          launch_gather_counters(d_desc_, d_slots_, (int)active.size(), d_counts_, s_exec_) !=
-              hipSuccess ||
-          hipMemcpyAsync(h_counts_, d_counts_, sizeof(int) * active.size(),
-                         hipMemcpyDeviceToHost, s_exec_) != hipSuccess ||
+          launch_gather_counters(d_desc_, d_slots_, ng, d_counts_, s_exec_) != hipSuccess ||
+          hipMemcpyAsync(h_counts_, d_counts_, sizeof(int) * ng, hipMemcpyDeviceToHost,
+                         s_exec_) != hipSuccess ||
           hipStreamSynchronize(s_exec_) != hipSuccess) {
         for (Shot* s : resident) fail(s);
         resident.clear();
@@ -357,7 +359,7 @@ class Engine {
       // (which do nothing past nt), until the graph is rebuilt anyway (new shots
       // active) or a queued request or an idle engine needs them back.
       std::vector<Shot*> keep;
-      for (size_t i = 0; i < active.size(); ++i) active[i]->counter = h_counts_[i];
+      for (int i = 0; i < ng; ++i) graph_shots_[i]->counter = h_counts_[i];
       for (Shot* s : resident) {
         if (s->state == ACTIVE && s->counter > s->g.nt) {
           finish(s);
@@ -480,8 +482,10 @@ class Engine {
     const size_t cap = gb > 0 ? gb : kCacheGroupBytes;
     std::vector<Group> groups;
     std::vector<int> slots;
+    graph_shots_.clear();
     for (Shot* s : active) {
       slots.push_back(s->slot);
+      graph_shots_.push_back(s);
       const int r = s->g.so / 2;
       const size_t b = (size_t)s->C.G.nfield * 12;  // two FP32 levels and v^2 dt^2
       size_t gi = 0;
@@ -594,6 +598,7 @@ class Engine {
   int* h_counts_ = nullptr;
   hipStream_t s_exec_ = nullptr, s_up_ = nullptr;
   hipGraphExec_t gexec_ = nullptr;
+  std::vector<Shot*> graph_shots_;  // shots of the current graph, in d_slots_ order
   std::vector<char> slot_used_;
   std::thread worker_, uploader_;
   std::mutex mu_, up_mu_;

@@ -125,10 +125,22 @@ class Engine:
         _bind().wave_engine_stats(self._h, ctypes.byref(s))
         return {k: getattr(s, k) for k, _ in WaveStats._fields_}
 
-    def drain(self, timeout_s=600.0):
-        st = _bind().wave_engine_drain(self._h, float(timeout_s))
-        if st != wave.OK:
-            raise TimeoutError("engine did not drain within %.0f s" % timeout_s)
+    def drain(self, timeout_s=600.0, log=None, every_s=5.0):
+        """Wait until nothing is queued or resident; with log, report the engine's
+        counters every every_s seconds while waiting."""
+        t_end = time.perf_counter() + timeout_s
+        while True:
+            left = t_end - time.perf_counter()
+            if left <= 0:
+                raise TimeoutError("engine did not drain within %.0f s" % timeout_s)
+            st = _bind().wave_engine_drain(self._h, float(min(left, every_s)))
+            if st == wave.OK:
+                return
+            if log is not None:
+                s = self.stats()
+                log("draining: completed %d queued %d resident %d replays %d graph builds %d"
+                    % (s["completed"], s["queued"], s["resident"], s["replays"],
+                       s["graph_builds"]))
 
     def close(self):
         if self._h is not None:
@@ -191,7 +203,7 @@ def run_poisson(engine, nreq, rate, seed, make=mixed_request, timeout_s=900.0, l
             log("submitted %d/%d" % (k + 1, nreq))
         if k + 1 < nreq:
             nxt = make(reqs_rng)
-    engine.drain(timeout_s)
+    engine.drain(timeout_s, log=log)
     recs = []
     for rid, upd in ids:
         st, t = engine.poll(rid)
