@@ -24,6 +24,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <climits>
 #include <atomic>
 #include <chrono>
 #include <condition_variable>
@@ -44,7 +45,8 @@ namespace wave {
 namespace {
 
 constexpr int kReplaySteps = 16;    // launches per group in one captured graph (even)
-constexpr double kSyncWork = 2e-3;  // GPU seconds of work enqueued between host syncs
+constexpr double kSyncWork = 2e-3;  // GPU seconds of work between host syncs while shots wait
+constexpr double kSyncWorkIdle = 10e-3;  // ... and while none waits
 constexpr double kUpdateRate = 250e9;  // grid-point updates per second, for that estimate
 constexpr int kEngineZChunk = 32;      // z-chunk length of resident shots
 // Shots stepped together in one run of kReplaySteps launches: their per-step arrays
@@ -334,11 +336,26 @@ class Engine {
         }
         dirty = false;
       }
-      // a few replays back to back, then read back the counters
+      // Replays back to back until the first resident shot can have finished (its
+      // remaining steps are known), within a time budget: short while shots are
+      // waiting to be admitted or promoted (they join at the next sync), longer
+      // otherwise; then read back the counters.
       double pts = 0;
-      for (Shot* s : active) pts += (double)s->g.nx * s->g.ny * s->g.nz;
+      int to_finish = INT_MAX;
+      for (Shot* s : active) {
+        pts += (double)s->g.nx * s->g.ny * s->g.nz;
+        const int left = std::max(1, s->g.nt + 1 - s->counter);
+        to_finish = std::min(to_finish, (left + kReplaySteps - 1) / kReplaySteps);
+      }
+      bool pending = resident.size() > active.size();
+      {
+        std::lock_guard<std::mutex> lk(mu_);
+        pending = pending || !queue_.empty();
+      }
       const double step_s = std::max(2e-6, pts / kUpdateRate);
-      const int reps = std::max(1, std::min(64, (int)(kSyncWork / (kReplaySteps * step_s))));
+      const double budget = pending ? kSyncWork : kSyncWorkIdle;
+      const int reps = std::max(
+          1, std::min({to_finish, 256, (int)(budget / (kReplaySteps * step_s))}));
       bool launched = true;
       for (int k = 0; k < reps && launched; ++k) launched = hipGraphLaunch(gexec_, s_exec_) == hipSuccess;
       // counters of the shots in the graph, in the slot order the last rebuild uploaded
@@ -357,7 +374,8 @@ class Engine {
       // Finished shots complete at once (traces copied back, latency recorded); their
       // slots and pool space stay reserved, and their table entries in the graph
       // (which do nothing past nt), until the graph is rebuilt anyway (new shots
-      // active) or a queued request or an idle engine needs them back.
+      // active), a queued request or an idle engine needs them back, or their idle
+      // workgroups reach a quarter of a launch.
       std::vector<Shot*> keep;
       for (int i = 0; i < ng; ++i) graph_shots_[i]->counter = h_counts_[i];
       for (Shot* s : resident) {
@@ -375,7 +393,10 @@ class Engine {
         std::lock_guard<std::mutex> lk(mu_);
         waiting = !queue_.empty();
       }
-      if (!finished.empty() && (waiting || !any_active)) {
+      // idle workgroups of finished shots: rebuild once they are a quarter of a launch
+      size_t idle_entries = 0;
+      for (Shot* s : finished) idle_entries += (size_t)s->C.T.nblocks + s->nsamp_blocks;
+      if (!finished.empty() && (waiting || !any_active || 4 * idle_entries > graph_entries_)) {
         for (Shot* s : finished) release(s);
         finished.clear();
         dirty = true;
@@ -498,11 +519,13 @@ class Engine {
     }
     std::vector<BatchEntry> all;
     std::vector<std::pair<int, std::pair<int, int>>> segs;  // radius, (offset, count)
+    graph_entries_ = 0;
     for (auto& G : groups) {
       segs.push_back({G.r, {(int)all.size(), (int)G.e.size()}});
       all.insert(all.end(), G.e.begin(), G.e.end());
     }
     if ((int)all.size() > table_cap_) return WAVE_ENOMEM;
+    graph_entries_ = all.size();
     cur_table_ ^= 1;
     BatchEntry* tab = d_table_[cur_table_];
     HIP_TRY(hipMemcpyAsync(tab, all.data(), all.size() * sizeof(BatchEntry),
@@ -599,6 +622,7 @@ class Engine {
   hipStream_t s_exec_ = nullptr, s_up_ = nullptr;
   hipGraphExec_t gexec_ = nullptr;
   std::vector<Shot*> graph_shots_;  // shots of the current graph, in d_slots_ order
+  size_t graph_entries_ = 0;        // table entries (workgroups) of one launch of each group
   std::vector<char> slot_used_;
   std::thread worker_, uploader_;
   std::mutex mu_, up_mu_;

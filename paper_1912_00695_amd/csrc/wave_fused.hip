@@ -325,12 +325,15 @@ __device__ __forceinline__ void fused2_tile(const Fused2Args& f, const int t) {
   if (za < za1) plane_step(za, 0);
 }
 
-#ifndef WAVE_F2_WPE
-#define WAVE_F2_WPE 1
-#endif
+// Occupancy per radius: at r = 3 the kernel needs 129 VGPRs unconstrained and fits 128
+// without spilling when asked for 4 waves per SIMD, which lets two 512-thread
+// workgroups share a CU (LDS 58.5 KB each): measured on MI355X, 100 steps, SO6:
+// 512^3 322 -> 382 Gpt/s, 448^3 295 -> 349 (one-step kernel 346 / 332). At r = 4
+// (158 VGPRs) the same request spills 72 bytes per lane and runs at 170-215 Gpt/s.
+constexpr int f2_waves_per_eu(int r) { return r == 3 ? 4 : 1; }
 template <int R, bool NT>
 __global__ void __launch_bounds__(F2_THREADS)
-__attribute__((amdgpu_waves_per_eu(R >= 3 ? WAVE_F2_WPE : 1)))
+__attribute__((amdgpu_waves_per_eu(f2_waves_per_eu(R))))
 fused2_kernel(const Fused2Args f) {
   const StepArgs& a = f.a;
   const int bid = blockIdx.x;
