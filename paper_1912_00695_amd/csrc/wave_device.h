@@ -6,11 +6,35 @@
 namespace wave {
 namespace {
 
+typedef float f4v __attribute__((ext_vector_type(4)));
+typedef _Float16 h4v __attribute__((ext_vector_type(4)));
+typedef unsigned u2v __attribute__((ext_vector_type(2)));
+
+// Global-memory view of a pointer. Every array the kernels address is device
+// global memory, but a pointer read from memory (the serving engine's shot
+// descriptors) is not known to be, and accesses through it compile to flat
+// instructions, which the compiler also has to count as possible LDS traffic:
+// each wait for an LDS read then waits for them too (a flat store per plane made
+// the batched kernel 13 % slower than the single-shot one on the same tiles).
+// (The host pass of the compilation sees these bodies too; there the qualifier
+// has no meaning and the view is the plain pointer.)
+#if defined(__HIP_DEVICE_COMPILE__)
+#define WAVE_GLOBAL_AS __attribute__((address_space(1)))
+#else
+#define WAVE_GLOBAL_AS
+#endif
+template <class T>
+__device__ __forceinline__ WAVE_GLOBAL_AS T* gmem(T* p) {
+  return (WAVE_GLOBAL_AS T*)p;
+}
+
 __device__ __forceinline__ float4 ld4(const float* p) {
-  return *reinterpret_cast<const float4*>(p);
+  const f4v v = *gmem(reinterpret_cast<const f4v*>(p));
+  return make_float4(v.x, v.y, v.z, v.w);
 }
 __device__ __forceinline__ void st4(float* p, const float4& v) {
-  *reinterpret_cast<float4*>(p) = v;
+  const f4v w = {v.x, v.y, v.z, v.w};
+  *gmem(reinterpret_cast<f4v*>(p)) = w;
 }
 __device__ __forceinline__ float comp(const float4& v, int i) {
   return i == 0 ? v.x : i == 1 ? v.y : i == 2 ? v.z : v.w;
@@ -33,16 +57,13 @@ __device__ __forceinline__ int remap_tile(int b, int nb) {
 // Element access per storage kind: 4 consecutive values (16- or 8-byte aligned)
 // or 1 value, widened to / narrowed from FP32 (round to nearest even). NT selects
 // non-temporal loads/stores (streamed once per step, not kept in the caches).
-typedef float f4v __attribute__((ext_vector_type(4)));
-typedef _Float16 h4v __attribute__((ext_vector_type(4)));
-typedef unsigned u2v __attribute__((ext_vector_type(2)));
 template <bool NT, class V>
 __device__ __forceinline__ V vload(const V* p) {
-  if constexpr (NT) return __builtin_nontemporal_load(p); else return *p;
+  if constexpr (NT) return __builtin_nontemporal_load(gmem(p)); else return *gmem(p);
 }
 template <bool NT, class V>
 __device__ __forceinline__ void vstore(V* p, const V& v) {
-  if constexpr (NT) __builtin_nontemporal_store(v, p); else *p = v;
+  if constexpr (NT) __builtin_nontemporal_store(v, gmem(p)); else *gmem(p) = v;
 }
 // Range-checked buffer loads (the CDNA buffer resource): a lane whose byte offset
 // is kOOB, or every lane of a resource with zero records, reads zeros without a
@@ -106,7 +127,7 @@ template <> struct Store<ST_F32> {
   __device__ static float4 widen(const Raw& v) { return make_float4(v.x, v.y, v.z, v.w); }
   template <bool NT = false>
   __device__ static float4 ld(const void* b, int64_t i) { return widen(ldr<NT>(b, i)); }
-  __device__ static float ld1(const void* b, int64_t i) { return static_cast<const float*>(b)[i]; }
+  __device__ static float ld1(const void* b, int64_t i) { return gmem(static_cast<const float*>(b))[i]; }
   template <bool NT = false>
   __device__ static void st(void* b, int64_t i, const float4& v) {
     f4v w;
@@ -138,7 +159,7 @@ template <> struct Store<ST_F16> {
   template <bool NT = false>
   __device__ static float4 ld(const void* b, int64_t i) { return widen(ldr<NT>(b, i)); }
   __device__ static float ld1(const void* b, int64_t i) {
-    return (float)static_cast<const _Float16*>(b)[i];
+    return (float)gmem(static_cast<const _Float16*>(b))[i];
   }
   template <bool NT = false>
   __device__ static void st(void* b, int64_t i, const float4& v) {
@@ -177,7 +198,7 @@ template <> struct Store<ST_BF16> {
   template <bool NT = false>
   __device__ static float4 ld(const void* b, int64_t i) { return widen(ldr<NT>(b, i)); }
   __device__ static float ld1(const void* b, int64_t i) {
-    return __uint_as_float((unsigned)static_cast<const unsigned short*>(b)[i] << 16);
+    return __uint_as_float((unsigned)gmem(static_cast<const unsigned short*>(b))[i] << 16);
   }
   template <bool NT = false>
   __device__ static void st(void* b, int64_t i, const float4& v) {
@@ -217,7 +238,8 @@ __device__ __forceinline__ float sample_point(const void* f, float dec, const in
                                               const float* w, int r) {
   float acc = 0.f;
 #pragma unroll
-  for (int c = 0; c < 8; ++c) acc = fmaf(w[8 * r + c], Store<ST>::ld1(f, idx[8 * r + c]) * dec, acc);
+  for (int c = 0; c < 8; ++c)
+    acc = fmaf(gmem(w)[8 * r + c], Store<ST>::ld1(f, gmem(idx)[8 * r + c]) * dec, acc);
   return acc;
 }
 }  // namespace

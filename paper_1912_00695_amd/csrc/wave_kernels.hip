@@ -35,6 +35,12 @@ namespace wave {
 #ifndef WAVE_PF2_MASK
 #define WAVE_PF2_MASK 0x0
 #endif
+// bit R of WAVE_ZUNROLL4_MASK: four planes per loop iteration, so the register
+// queue shifts once per four planes (fewer moves per plane, more code); measured
+// at 256^3: +3 % at SO16 and SO24, none at SO12, -1 % at SO8
+#ifndef WAVE_ZUNROLL4_MASK
+#define WAVE_ZUNROLL4_MASK 0x1F00  // radius 8..12
+#endif
 // bit R of WAVE_HRING_MASK: load the xy-halo of each plane R planes ahead (with the
 // queue head of the same plane) and park it in LDS until the plane is staged; by
 // default only in launches without non-temporal streams (WAVE_HRING_NT=1: in those
@@ -47,6 +53,13 @@ namespace wave {
 #endif
 constexpr bool zunroll2(int r) { return ((WAVE_ZUNROLL_MASK) >> r) & 1; }
 constexpr bool prefetch2(int r) { return ((WAVE_PF2_MASK) >> r) & 1; }
+constexpr bool zunroll4(int r) { return ((WAVE_ZUNROLL4_MASK) >> r) & 1; }
+// bit R of WAVE_BSTORE_MASK: buffer stores of the step's outputs (else predicated
+// global stores)
+#ifndef WAVE_BSTORE_MASK
+#define WAVE_BSTORE_MASK 0x0
+#endif
+constexpr bool bstore(int r) { return ((WAVE_BSTORE_MASK) >> r) & 1; }
 constexpr bool halo_ring(int r) { return ((WAVE_HRING_MASK) >> r) & 1; }
 
 // One tile of one step: the z-sweep of a TX x TY column block over one z-chunk.
@@ -77,6 +90,7 @@ __device__ __forceinline__ void step_tile(const StepArgs& a, const int t, const 
   // does not fit the Infinity Cache, swept in several rounds of workgroups) it
   // ranged from +1 % to -8 % and is off.
   constexpr bool HRG = halo_ring(R) && (!NT || WAVE_HRING_NT);
+  constexpr bool BSTORE = bstore(R);
   using Raw = typename Store<ST>::Raw;
   __shared__ Raw hbuf[HRG ? R + 1 : 1][HRG ? NH : 1];
   const auto hslot = [](const int p) { return p % (R + 1); };  // p >= 0
@@ -149,7 +163,7 @@ __device__ __forceinline__ void step_tile(const StepArgs& a, const int t, const 
 
   // Sponge factors: b = bx[x] + by[y] + bz[z].
   const float4 bxv = colok ? ld4(a.bx + x0) : zero4;
-  const float byv = y < ny ? a.by[y] : 0.f;
+  const float byv = y < ny ? gmem(a.by)[y] : 0.f;
 
   // Loads are kept raw until every load of a batch has been issued, then widened
   // (and decoded) in one go, so that no conversion waits for a single load.
@@ -208,18 +222,19 @@ __device__ __forceinline__ void step_tile(const StepArgs& a, const int t, const 
     }
   }
   inj[tid] = zero4;
-  if (tid < z1 - z0) bzs[tid] = a.bz[z0 + tid];
+  if (tid < z1 - z0) bzs[tid] = gmem(a.bz)[z0 + tid];
   __syncthreads();
 
   // Injection entries of this tile (sorted by plane); ez is the plane of the next
   // group, kept in a register so the per-plane test needs no load.
   int e = 0, e_end = 0, ez = INT_MAX, eg = 0;  // eg: end of the group at plane ez
+  const auto* ent = gmem(a.ent);
   if (a.tile_beg != nullptr) {
-    e = a.tile_beg[t];
-    e_end = a.tile_beg[t + 1];
+    e = gmem(a.tile_beg)[t];
+    e_end = gmem(a.tile_beg)[t + 1];
     if (e < e_end) {
-      ez = a.ent[e].z;
-      eg = a.ent[e].grp_end;
+      ez = ent[e].z;
+      eg = ent[e].grp_end;
     }
   }
 
@@ -298,13 +313,14 @@ __device__ __forceinline__ void step_tile(const StepArgs& a, const int t, const 
     // Fused injection at this plane (uniform branch).
     if (z == ez) {
       for (int i = e + tid; i < eg; i += NTHREADS) {
-        const InjEntry en = a.ent[i];
+        const InjEntry en = ent[i];
+        const auto* row = gmem(a.trace_row);
         float s = 0.f;
         if (en.tidx >= 0) {  // single term, carried in the entry
-          s = fmaf(en.w, a.trace_row[en.tidx], 0.f);
+          s = fmaf(en.w, row[en.tidx], 0.f);
         } else {
           for (int c = en.csr_beg; c < en.csr_end; ++c)
-            s = fmaf(a.csr_w[c], a.trace_row[a.csr_idx[c]], s);
+            s = fmaf(gmem(a.csr_w)[c], row[gmem(a.csr_idx)[c]], s);
         }
         reinterpret_cast<float*>(inj)[en.local] = s;
       }
@@ -315,8 +331,8 @@ __device__ __forceinline__ void step_tile(const StepArgs& a, const int t, const 
       e = eg;
       ez = INT_MAX;
       if (e < e_end) {
-        ez = a.ent[e].z;
-        eg = a.ent[e].grp_end;
+        ez = ent[e].z;
+        eg = ent[e].grp_end;
       }
     }
 
@@ -376,7 +392,33 @@ __device__ __forceinline__ void step_tile(const StepArgs& a, const int t, const 
       }
     }
     }
-    if (colok) {
+    if constexpr (BSTORE) {
+      // buffer stores on every path (lanes outside the grid have offset kOOB): the
+      // plane's resource carries the address, no per-lane 64-bit arithmetic
+      if constexpr (ST == ST_F32) {
+        Store<ST>::template stb<NT>(rs_at(a.out, z, ES, pbytes, true), vo_col, o);
+      } else {
+        if (colok) {
+          mx_u = fmaxf(mx_u, fmaxf(fmaxf(fabsf(o.x), fabsf(o.y)), fmaxf(fabsf(o.z), fabsf(o.w))));
+          if constexpr (DIFF)
+            mx_d = fmaxf(mx_d, fmaxf(fmaxf(fabsf(dn.x), fabsf(dn.y)), fmaxf(fabsf(dn.z), fabsf(dn.w))));
+        }
+        if constexpr (DIFF) {
+          Store<ST>::template stb<NT>(rs_at(a.out_u, z, ES, pbytes, true), vo_col, mul4(o, enc_u));
+          Store<ST>::template stb<NT>(rs_at(a.out, z, ES, pbytes, true), vo_col, mul4(dn, enc_d));
+        } else {
+          Store<ST>::template stb<NT>(rs_at(a.out, z, ES, pbytes, true), vo_col, mul4(o, enc_u));
+        }
+      }
+      if constexpr (GRAD) {
+        const float4 uf = Store<ST_F32>::widen(ufc);
+        float4 gv = Store<ST_F32>::widen(grc);
+        const float4 f = a.acc_image ? q[R] : src;
+        gv.x = fmaf(uf.x, f.x, gv.x); gv.y = fmaf(uf.y, f.y, gv.y);
+        gv.z = fmaf(uf.z, f.z, gv.z); gv.w = fmaf(uf.w, f.w, gv.w);
+        Store<ST_F32>::template stb<false>(rs_f32(a.grad, z, true), vo_c2, gv);
+      }
+    } else if (colok) {
       const int64_t at = z * plane + col;
       if constexpr (ST == ST_F32) {
         Store<ST>::template st<NT>(a.out, at, o);
@@ -434,7 +476,15 @@ __device__ __forceinline__ void step_tile(const StepArgs& a, const int t, const 
   Ahead fa, fb;
   if constexpr (PF2) fetch(z0 + 1, fa);
   int z = z0;
-  if constexpr (PF2 || zunroll2(R)) {
+  if constexpr (zunroll4(R) && !PF2) {
+    for (; z + 3 < z1; z += 4) {
+      plane_step(z, 0, fa, fb);
+      plane_step(z + 1, 1, fb, fa);
+      plane_step(z + 2, 0, fa, fb);
+      plane_step(z + 3, 1, fb, fa);
+    }
+  }
+  if constexpr (PF2 || zunroll2(R) || zunroll4(R)) {
     for (; z + 1 < z1; z += 2) {
       plane_step(z, 0, fa, fb);
       plane_step(z + 1, 1, fb, fa);
