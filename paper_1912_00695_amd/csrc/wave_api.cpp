@@ -371,16 +371,19 @@ bool want_fused(const wave_grid* g, int* zchunk) {
   return g->so / 2 <= 3 && npts >= kFusedMinPoints[g->so / 2];
 }
 
-// Source tables of the two-step kernel: for every tile, the grid points of its
-// extended region (x in [xt - 4, xt + TX + 4), y in [yt - r, yt + TY + r), z in
-// [z0 - r, z1 + r)), with local index row * (TX + 8) + column in that region.
-// A point near a tile edge appears in the tables of every tile whose region
-// holds it; each copy carries its own (point, weight) terms in the same order.
+// Source tables of the two-step kernel: for every two-step tile (f2_tiles_y(r)
+// one-step tiles of T stacked along y, TY2 = f2_tiles_y(r) * TY rows), the grid
+// points of its extended region (x in [xt - 4, xt + TX + 4), y in [yt - r, yt +
+// TY2 + r), z in [z0 - r, z1 + r)), with local index row * (TX + 8) + column in
+// that region. A point near a tile edge appears in the tables of every tile whose
+// region holds it; each copy carries its own (point, weight) terms in the same order.
 void build_ext_tables(const wave_grid* g, const Geom& G, const Tiling& T, int r, const double* xyz,
                       int np, const PointTables& P, Blob& B) {
   constexpr int XE = 4;
+  const int TY2 = f2_tiles_y(r) * TY;
+  const int nty = (T.ntile_y + f2_tiles_y(r) - 1) / f2_tiles_y(r);
   int* tile_beg = B.at<int>(P.tile_beg);
-  const int ntiles = T.nblocks;
+  const int ntiles = T.ntile_x * nty * T.nchunk;
   std::fill(tile_beg, tile_beg + ntiles + 1, 0);
   struct Key {
     int tile, z, local;
@@ -398,14 +401,14 @@ void build_ext_tables(const wave_grid* g, const Geom& G, const Tiling& T, int r,
       for (int tx = std::max(0, i / TX - 1); tx <= std::min(T.ntile_x - 1, i / TX + 1); ++tx) {
         const int xt = tx * TX;
         if (i < xt - XE || i >= xt + TX + XE) continue;
-        for (int ty = std::max(0, j / TY - 1); ty <= std::min(T.ntile_y - 1, j / TY + 1); ++ty) {
-          const int yt = ty * TY;
-          if (j < yt - r || j >= yt + TY + r) continue;
+        for (int ty = std::max(0, j / TY2 - 1); ty <= std::min(nty - 1, j / TY2 + 1); ++ty) {
+          const int yt = ty * TY2;
+          if (j < yt - r || j >= yt + TY2 + r) continue;
           for (int zc = std::max(0, z / T.zchunk - 1);
                zc <= std::min(T.nchunk - 1, z / T.zchunk + 1); ++zc) {
             const int z0 = zc * T.zchunk, z1 = std::min(z0 + T.zchunk, G.nz);
             if (z < z0 - r || z >= z1 + r) continue;
-            const int tile = (zc * T.ntile_y + ty) * T.ntile_x + tx;
+            const int tile = (zc * nty + ty) * T.ntile_x + tx;
             const int local = (j - (yt - r)) * (TX + 2 * XE) + (i - (xt - XE));
             uniq[Key{tile, z, local}].push_back({p, (float)w[k]});
           }
@@ -741,6 +744,10 @@ int forward_fused(Ctx& C, const float* wavelet, int nsrc, int nrec, float* rec_o
   const PointTables& PR = C.L.pts[1];
   Fused2Args f{};
   f.a = base_args(C);
+  // launch in two-step tiles; the tile tables stay in the one-step tiling
+  f.ntile_y1 = C.T.ntile_y;
+  f.a.ntile_y = (C.T.ntile_y + f2_tiles_y(r) - 1) / f2_tiles_y(r);
+  f.a.nstencil_blocks = C.T.ntile_x * f.a.ntile_y * C.T.nchunk;
   int cur = 0, prv = 1, o1 = 2, o2 = 3;
   int n = 0;
   for (; n + 2 <= g->nt; n += 2) {

@@ -4,8 +4,9 @@
 // The single-step kernel moves 16 bytes per point and step (read u^n, u^{n-1},
 // c2; write u^{n+1}) and is bandwidth-bound at every space order. This kernel
 // reads u^n, u^{n-1} and c2 once and writes u^{n+1} and u^{n+2}: 20 bytes per
-// point for two steps. Each workgroup owns a TX x TY tile and a z-chunk and runs
-// two pipelined stages down the chunk:
+// point for two steps. Each workgroup owns a tile of TX x TY2 points (TY2 = K TY,
+// K = f2_tiles_y(r) one-step tiles stacked along y) and a z-chunk and runs two
+// pipelined stages down the chunk:
 //   stage A  v = u^{n+1} at plane za on the tile extended by XH columns and R rows
 //            on each side (the region E), from a register queue of u^n planes
 //            za-R..za+R and an LDS copy of plane za with a further ring;
@@ -13,7 +14,8 @@
 //            planes zb-R..zb+R and an LDS copy of v at plane zb on E.
 // Stage A runs R planes beyond the chunk at both ends (and stage B needs u^n
 // beyond that), so each chunk recomputes 2R planes of v and re-reads 4R planes of
-// u^n; the extended region costs (TX+2XH)(TY+2R)/(TX TY) times the stage-A work.
+// u^n; the extended region costs (TX+2XH)(TY2+2R)/(TX TY2) times the stage-A work
+// (1.69 at K = 1, r = 4; 1.41 at K = 2).
 // Both are paid in arithmetic and L2 traffic, which this bandwidth-bound scheme
 // has to spare. Every point's update is the same expression, in the same order,
 // as in the single-step kernel.
@@ -41,12 +43,15 @@ constexpr int F2_UROW4 = NTX + 4 * F2_XH4;  // float4 per row of the LDS copy of
 template <int R, bool NT>
 __device__ __forceinline__ void fused2_tile(const Fused2Args& f, const int t) {
   const StepArgs& a = f.a;
-  constexpr int EY = TY + 2 * R;                    // rows of E
+  constexpr int K = f2_tiles_y(R);                  // one-step tiles per tile, along y
+  constexpr int TY2 = K * TY;                       // rows of the tile
+  constexpr int NTH = f2_threads(R);
+  constexpr int EY = TY2 + 2 * R;                   // rows of E
   constexpr int NE = F2_EX4 * EY;                   // E columns (threads with a column)
-  constexpr int UROWS = TY + 4 * R;                 // rows of the LDS copy of u^n
+  constexpr int UROWS = TY2 + 4 * R;                // rows of the LDS copy of u^n
   constexpr int NRING = 2 * R * F2_UROW4 + EY * 2 * F2_XH4;  // u^n items around E
   static_assert(TX + 2 * F2_XH == 4 * F2_EX4, "E rows hold whole float4");
-  static_assert(R <= F2_XH && NE <= F2_THREADS && NRING <= F2_THREADS, "fused tile shape");
+  static_assert(R <= F2_XH && NE <= NTH && NRING <= NTH, "fused tile shape");
   __shared__ float4 ulds[2][UROWS * F2_UROW4];
   __shared__ float4 vlds[EY * F2_EX4];
   __shared__ float4 inj[EY * F2_EX4];
@@ -57,14 +62,14 @@ __device__ __forceinline__ void fused2_tile(const Fused2Args& f, const int t) {
   // heads (so the ring is served by L2); and c2 of the tile columns at planes
   // za-R .. za for stage B (stage A's own load, reused).
   __shared__ float4 ringbuf[R + 1][NRING];
-  __shared__ float4 cring[R + 1][TY * NTX];
+  __shared__ float4 cring[R + 1][TY2 * NTX];
   const auto slot = [](const int z) { return ((z % (R + 1)) + (R + 1)) % (R + 1); };
 
   const int tx_t = t % a.ntile_x;
   const int rest = t / a.ntile_x;
   const int ty_t = rest % a.ntile_y;
   const int zc = rest / a.ntile_y;
-  const int xt = tx_t * TX, yt = ty_t * TY;
+  const int xt = tx_t * TX, yt = ty_t * TY2;
   const int nx = a.g.nx, ny = a.g.ny, nz = a.g.nz;
   const int64_t plane = a.g.plane;
   const int z0 = zc * a.zchunk;
@@ -75,7 +80,7 @@ __device__ __forceinline__ void fused2_tile(const Fused2Args& f, const int t) {
   const int ex = act ? tid % F2_EX4 : 0, ey = act ? tid / F2_EX4 : 0;
   const int x0 = xt - F2_XH + 4 * ex, y = yt - R + ey;
   const bool colok = act && x0 >= 0 && x0 < nx && y >= 0 && y < ny;
-  const bool inner = act && ex >= F2_XH4 && ex < F2_XH4 + NTX && ey >= R && ey < R + TY;
+  const bool inner = act && ex >= F2_XH4 && ex < F2_XH4 + NTX && ey >= R && ey < R + TY2;
   const int col = colok ? y * a.g.pitch + x0 : 0;
   const float4 zero4 = make_float4(0.f, 0.f, 0.f, 0.f);
 
@@ -142,17 +147,18 @@ __device__ __forceinline__ void fused2_tile(const Fused2Args& f, const int t) {
 #pragma unroll
   for (int s = 0; s <= 2 * R; ++s) vq[s] = zero4;
   if (act) inj[tid] = zero4;
-  for (int i = tid; i < za1 - za0; i += F2_THREADS) {
+  for (int i = tid; i < za1 - za0; i += NTH) {
     const int zz = za0 + i;
     bzs[i] = (zz >= 0 && zz < nz) ? a.bz[zz] : 0.f;
   }
   __syncthreads();
 
   // Injection entries (sorted by plane) of the extended tile (stage A) and of the
-  // tile (stage B); eza / ezb hold the plane of the next group of each, so the
-  // per-plane tests need no load.
-  int ea = 0, ea_end = 0, eb = 0, eb_end = 0, eza = INT_MAX, ezb = INT_MAX;
-  int ega = 0, egb = 0;  // ends of the groups at planes eza, ezb
+  // K one-step tiles that make up the tile (stage B, from the one-step tables);
+  // eza / ezb[k] hold the plane of the next group of each, so the per-plane tests
+  // need no load.
+  int ea = 0, ea_end = 0, eza = INT_MAX, ega = 0;  // ega: end of the group at eza
+  int eb[K], eb_end[K], ezb[K], egb[K];
   if (f.etile_beg != nullptr) {
     ea = f.etile_beg[t];
     ea_end = f.etile_beg[t + 1];
@@ -161,12 +167,21 @@ __device__ __forceinline__ void fused2_tile(const Fused2Args& f, const int t) {
       ega = f.eent[ea].grp_end;
     }
   }
-  if (a.tile_beg != nullptr) {
-    eb = a.tile_beg[t];
-    eb_end = a.tile_beg[t + 1];
-    if (eb < eb_end) {
-      ezb = a.ent[eb].z;
-      egb = a.ent[eb].grp_end;
+#pragma unroll
+  for (int k = 0; k < K; ++k) {
+    eb[k] = 0;
+    eb_end[k] = 0;
+    ezb[k] = INT_MAX;
+    egb[k] = 0;
+    const int ty1 = K * ty_t + k;
+    if (a.tile_beg != nullptr && ty1 < f.ntile_y1) {
+      const int t1 = (zc * f.ntile_y1 + ty1) * a.ntile_x + tx_t;
+      eb[k] = a.tile_beg[t1];
+      eb_end[k] = a.tile_beg[t1 + 1];
+      if (eb[k] < eb_end[k]) {
+        ezb[k] = a.ent[eb[k]].z;
+        egb[k] = a.ent[eb[k]].grp_end;
+      }
     }
   }
 
@@ -229,7 +244,7 @@ __device__ __forceinline__ void fused2_tile(const Fused2Args& f, const int t) {
   auto inject = [&](const InjEntry* ent, const int* cidx, const float* cw, const float* row,
                     int& e, const int e_end, int& ez, int& eg, const bool mine,
                     const int slot) {
-    for (int i = e + tid; i < eg; i += F2_THREADS) {
+    for (int i = e + tid; i < eg; i += NTH) {
       const InjEntry en = ent[i];
       float s = 0.f;
       if (en.tidx >= 0) {  // single term, carried in the entry
@@ -295,10 +310,43 @@ __device__ __forceinline__ void fused2_tile(const Fused2Args& f, const int t) {
     if (doB) {
       float lapb[4] = {0.f, 0.f, 0.f, 0.f};
       if (inner) laplacian(vq, vlds, crowB, F2_EX4, lapb);
-      if (zb == ezb) {
-        const float4 iv =
-            inject(a.ent, a.csr_idx, a.csr_w, a.trace_row, eb, eb_end, ezb, egb, inner, slotB);
-        lapb[0] += iv.x; lapb[1] += iv.y; lapb[2] += iv.z; lapb[3] += iv.w;
+      bool injb = false;
+#pragma unroll
+      for (int k = 0; k < K; ++k) injb = injb || zb == ezb[k];
+      if (injb) {  // uniform
+        // scatter the plane's groups of every sub-tile (sub-tile k holds tile rows
+        // k*TY .. k*TY+TY-1, so its local indices are offset by k*TY*TX)
+#pragma unroll
+        for (int k = 0; k < K; ++k) {
+          if (zb != ezb[k]) continue;
+          for (int i = eb[k] + tid; i < egb[k]; i += NTH) {
+            const InjEntry en = a.ent[i];
+            float s = 0.f;
+            if (en.tidx >= 0) {
+              s = fmaf(en.w, a.trace_row[en.tidx], 0.f);
+            } else {
+              for (int c = en.csr_beg; c < en.csr_end; ++c)
+                s = fmaf(a.csr_w[c], a.trace_row[a.csr_idx[c]], s);
+            }
+            reinterpret_cast<float*>(inj)[k * TY * TX + en.local] = s;
+          }
+        }
+        __syncthreads();
+        if (inner) {
+          const float4 iv = inj[slotB];
+          inj[slotB] = zero4;
+          lapb[0] += iv.x; lapb[1] += iv.y; lapb[2] += iv.z; lapb[3] += iv.w;
+        }
+#pragma unroll
+        for (int k = 0; k < K; ++k) {
+          if (zb != ezb[k]) continue;
+          eb[k] = egb[k];
+          ezb[k] = INT_MAX;
+          if (eb[k] < eb_end[k]) {
+            ezb[k] = a.ent[eb[k]].z;
+            egb[k] = a.ent[eb[k]].grp_end;
+          }
+        }
       }
       w = update(vq[R], q[0], cring[slot(zb)][slotB], bzs[max(zb - za0, 0)], lapb);
     }
@@ -332,13 +380,13 @@ __device__ __forceinline__ void fused2_tile(const Fused2Args& f, const int t) {
 // (158 VGPRs) the same request spills 72 bytes per lane and runs at 170-215 Gpt/s.
 constexpr int f2_waves_per_eu(int r) { return r == 3 ? 4 : 1; }
 template <int R, bool NT>
-__global__ void __launch_bounds__(F2_THREADS)
+__global__ void __launch_bounds__(f2_threads(R))
 __attribute__((amdgpu_waves_per_eu(f2_waves_per_eu(R))))
 fused2_kernel(const Fused2Args f) {
   const StepArgs& a = f.a;
   const int bid = blockIdx.x;
   if (bid >= a.nstencil_blocks) {
-    const int r = (bid - a.nstencil_blocks) * F2_THREADS + threadIdx.x;
+    const int r = (bid - a.nstencil_blocks) * f2_threads(R) + threadIdx.x;
     if (r < a.nsamp) {
       if (a.samp_out != nullptr)
         a.samp_out[r] = sample_point<ST_F32>(a.cur, 1.f, a.samp_idx, a.samp_w, r);
@@ -353,8 +401,9 @@ fused2_kernel(const Fused2Args f) {
 
 template <int R>
 hipError_t launch_fused2_r(const Fused2Args& f, bool nt, hipStream_t s) {
-  const int nsb = (f.a.nsamp + F2_THREADS - 1) / F2_THREADS;
-  const dim3 grid(f.a.nstencil_blocks + (f.a.nsamp > 0 ? nsb : 0)), block(F2_THREADS);
+  constexpr int nth = f2_threads(R);
+  const int nsb = (f.a.nsamp + nth - 1) / nth;
+  const dim3 grid(f.a.nstencil_blocks + (f.a.nsamp > 0 ? nsb : 0)), block(nth);
   if (nt)
     hipLaunchKernelGGL((fused2_kernel<R, true>), grid, block, 0, s, f);
   else

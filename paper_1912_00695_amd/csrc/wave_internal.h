@@ -110,9 +110,18 @@ struct StepArgs {
 // injection tables with trace_row = step n+1's samples (added to u^{n+2});
 // sampling of cur into samp_out. The extended-tile tables inject step n's samples
 // into u^{n+1} over each tile's extended region.
-constexpr int F2_THREADS = 512;
+// A two-step tile is K one-step tiles stacked along y (TX x K*TY points): K = 1
+// (512 threads) up to radius 3, K = 2 (768 threads) at radius 4, where the taller
+// tile halves the extended region's overhead per point and a workgroup has 12
+// waves. The launch's tile counts (a.ntile_y, a.nstencil_blocks) are in two-step
+// tiles; the tile injection tables are the one-step tiling's (ntile_y1 tiles along
+// y), read per sub-tile.
+constexpr int f2_tiles_y(int r) { return r == 4 ? 2 : 1; }
+constexpr int f2_threads(int r) { return r == 4 ? 768 : 512; }
+constexpr int F2_THREADS_MAX = 768;
 struct Fused2Args {
   StepArgs a;
+  int ntile_y1;              // one-step tiles along y (the tile tables' tiling)
   float* out2;               // u^{n+2}
   const int* etile_beg;      // [ntiles + 1] entries over the extended tiles
   const InjEntry* eent;      // local = row * (TX + 8) + column within the extended tile

@@ -1,5 +1,5 @@
-// Host-only self-test of the solver's injection and sampling tables and of its
-// z-chunk policy (paper_1912_00695_amd/csrc/wave_api.cpp, compiled into this test
+// Host-only self-test of the solver's injection and sampling tables, the
+// two-step kernel's extended-region tables and the z-chunk policy (paper_1912_00695_amd/csrc/wave_api.cpp, compiled into this test
 // with the host compiler; the kernels' launchers resolve against libwave.so but
 // none is called). For random point sets -- on grid points, off them, repeated,
 // on tile and chunk edges -- the tables are checked against a brute-force
@@ -128,6 +128,86 @@ static void check_tables(const wave_grid& g, int zchunk, const std::vector<doubl
   CHECK(covered == want);
 }
 
+// Extended-region tables of the two-step kernel (build_ext_tables), against a
+// reference from the definition: a two-step tile is f2_tiles_y(r) one-step tiles
+// stacked along y (TY2 rows); a corner (i, j, z) belongs to every two-step tile
+// whose region x in [xt - 4, xt + TX + 4), y in [yt - r, yt + TY2 + r), z in
+// [z0 - r, z1 + r) holds it (all tiles scanned), with local index
+// (j - yt + r) * (TX + 8) + (i - xt + 4).
+static void check_ext_tables(wave_grid g, int zchunk, const std::vector<double>& xyz) {
+  const int r = g.so / 2;
+  const Geom G = make_geom(&g);
+  const Tiling T = make_tiling(G, zchunk, false);
+  const int np = (int)xyz.size() / 3;
+  const Layout L = make_layout(&g, np, 0, WAVE_MODE_FORWARD, 0, true);
+  CHECK(L.fused);
+  Blob B;
+  B.base = L.tables_beg;
+  const size_t size = L.tables_end - L.tables_beg;
+  B.bytes = new char[size];
+  std::memset(B.bytes, 0xA5, size);
+  build_ext_tables(&g, G, T, r, xyz.data(), np, L.epts, B);
+
+  const int TY2 = f2_tiles_y(r) * TY;
+  const int nty = (G.ny + TY2 - 1) / TY2;
+  const int ntiles = T.ntile_x * nty * T.nchunk;
+  std::map<RefKey, std::vector<RefTerm>> ref;
+  for (int p = 0; p < np; ++p) {
+    const double f[3] = {xyz[3 * p] / g.hx, xyz[3 * p + 1] / g.hy, xyz[3 * p + 2] / g.hz};
+    int base[3];
+    double t[3];
+    for (int a = 0; a < 3; ++a) {
+      base[a] = (int)std::floor(f[a]);
+      t[a] = f[a] - base[a];
+    }
+    for (int c = 0; c < 8; ++c) {
+      const int d[3] = {c & 1, (c >> 1) & 1, (c >> 2) & 1};
+      double w = 1.0;
+      for (int a = 0; a < 3; ++a) w *= d[a] ? t[a] : 1.0 - t[a];
+      if (w == 0.0) continue;
+      const int i = base[0] + d[0], j = base[1] + d[1], z = base[2] + d[2];
+      for (int tile = 0; tile < ntiles; ++tile) {
+        const int xt = (tile % T.ntile_x) * TX, yt = ((tile / T.ntile_x) % nty) * TY2;
+        const int z0 = (tile / (T.ntile_x * nty)) * T.zchunk;
+        const int z1 = std::min(z0 + T.zchunk, G.nz);
+        if (i < xt - 4 || i >= xt + TX + 4 || j < yt - r || j >= yt + TY2 + r || z < z0 - r ||
+            z >= z1 + r)
+          continue;
+        ref[RefKey{tile, z, (j - yt + r) * (TX + 8) + (i - xt + 4)}].push_back(
+            RefTerm{p, (float)w});
+      }
+    }
+  }
+  const int* tb = B.at<int>(L.epts.tile_beg);
+  const InjEntry* ent = B.at<InjEntry>(L.epts.ent);
+  const int* cidx = B.at<int>(L.epts.csr_idx);
+  const float* cw = B.at<float>(L.epts.csr_w);
+  CHECK(tb[0] == 0 && tb[ntiles] == (int)ref.size());
+  int e = 0, c = 0;
+  for (const auto& kv : ref) {
+    const int tile = std::get<0>(kv.first);
+    CHECK(tb[tile] <= e && e < tb[tile + 1]);
+    const InjEntry& en = ent[e];
+    CHECK(en.z == std::get<1>(kv.first) && en.local == std::get<2>(kv.first));
+    CHECK(en.csr_beg == c && en.csr_end == c + (int)kv.second.size());
+    for (const RefTerm& q : kv.second) {
+      CHECK(cidx[c] == q.p && cw[c] == q.w);
+      ++c;
+    }
+    if (kv.second.size() == 1) {
+      CHECK(en.tidx == kv.second[0].p && en.w == kv.second[0].w);
+    } else {
+      CHECK(en.tidx == -1);
+    }
+    int q = e;
+    while (q < tb[tile + 1] && ent[q].z == en.z) ++q;
+    CHECK(en.grp_end == q);
+    ++e;
+  }
+  for (int t = 0; t < ntiles; ++t) CHECK(tb[t] <= tb[t + 1]);
+  CHECK((size_t)e <= (size_t)64 * np);  // the layout's bound on entries
+}
+
 static wave_grid grid(int nx, int ny, int nz) {
   wave_grid g{};
   g.nx = nx;
@@ -201,6 +281,37 @@ static void test_tables() {
   std::printf("tables: %d cases\n", cases + 1);
 }
 
+static void test_ext_tables() {
+  std::mt19937_64 rng(11);
+  std::uniform_real_distribution<double> U(0.0, 1.0);
+  const int shapes[][3] = {{97, 37, 23}, {160, 48, 70}, {130, 70, 41}};
+  int cases = 0;
+  for (const auto& s : shapes) {
+    for (int so : {2, 4, 6, 8}) {
+      wave_grid g = grid(s[0], s[1], s[2]);
+      g.so = so;
+      for (int zc : {8, 13}) {
+        std::vector<double> xyz;
+        for (int p = 0; p < 120; ++p) {
+          double f[3] = {U(rng) * (g.nx - 1), U(rng) * (g.ny - 1), U(rng) * (g.nz - 1)};
+          if (p % 3 == 0)
+            for (double& v : f) v = std::floor(v);  // on grid points
+          if (p % 4 == 1) {  // on and next to tile edges: x 63/64, y 15/16 and 31/32
+            f[0] = std::min<double>(g.nx - 1, 63 + (p % 3) * 0.5);
+            f[1] = std::min<double>(g.ny - 1, (p % 8 < 4 ? 15.0 : 31.0) + (p % 2) * 0.5);
+          }
+          xyz.push_back(f[0] * g.hx);
+          xyz.push_back(f[1] * g.hy);
+          xyz.push_back(f[2] * g.hz);
+        }
+        check_ext_tables(g, zc, xyz);
+        ++cases;
+      }
+    }
+  }
+  std::printf("ext tables: %d cases\n", cases);
+}
+
 static void test_tiling() {
   const auto zc = [](int n, bool naive16) {
     wave_grid g = grid(n, n, n);
@@ -228,6 +339,7 @@ static void test_tiling() {
 
 int main() {
   test_tables();
+  test_ext_tables();
   test_tiling();
   std::printf("OK\n");
   return 0;

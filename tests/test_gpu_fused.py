@@ -57,13 +57,16 @@ def test_fused_equals_single_step_path(so):
 
 
 def test_fused_sources_on_tile_and_chunk_edges():
-    """Sources and receivers on and next to tile edges (x = 63, 64; y = 15, 16) and
-    z-chunk edges (z = 31, 32 with 8-plane chunks), where the extended-region
-    injection tables of neighbouring tiles overlap; SO8, 160 x 48 x 70."""
+    """Sources and receivers on and next to tile edges (x = 63, 64; y = 15, 16
+    between the two one-step tiles of a two-step tile at SO8, y = 31, 32 between
+    two-step tiles, y = 47 in a two-step tile with one one-step tile) and z-chunk
+    edges (z = 31, 32 with 8-plane chunks), where the extended-region injection
+    tables of neighbouring tiles overlap; SO8, 160 x 48 x 70."""
     n, h = (160, 48, 70), (10.0, 10.0, 10.0)
     vel = inputs.smooth_random_range(n, 1500.0, 2500.0, 8.0, seed=31)
     c = Case(n, h, 8, 36, vel, 2500.0, nbl=(6,) * 6)
-    pts = [(63, 15, 31), (64, 16, 32), (63.5, 15.5, 31.5), (127.2, 31.7, 63.9), (2.0, 46.5, 40.0)]
+    pts = [(63, 15, 31), (64, 16, 32), (63.5, 15.5, 31.5), (127.2, 31.7, 63.9), (2.0, 46.5, 40.0),
+           (64, 32, 20), (10, 31, 9), (100, 47, 50), (65.25, 31.5, 44.0)]
     c.src = np.array([[p[0] * h[0], p[1] * h[1], p[2] * h[2]] for p in pts])
     c.wavelet = np.random.default_rng(32).standard_normal((c.nt, len(pts))).astype(np.float32)
     c.rec = np.concatenate([c.src, inputs.random_points(n, h, 30, 33)])
