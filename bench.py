@@ -237,7 +237,10 @@ def reduced_precision_leg(dev):
     gold = np.load(gold, allow_pickle=False) if os.path.exists(gold) else None
     res, ref = {}, None
     for name, st in (("f32", 0), ("f16_diff", 17), ("bf16_diff", 18), ("f16", 1), ("bf16", 2)):
-        g = wave.make_grid(n, h, 8, dt, nt, (40,) * 6, vmax=vmax, storage=st)
+        # every format on the one-step kernel (the FP32 default here is the two-step
+        # kernel, which has no 16-bit form)
+        g = wave.make_grid(n, h, 8, dt, nt, (40,) * 6, vmax=vmax, storage=st,
+                           path=wave.PATH_ONE_STEP)
         ws = torch.empty(wave.workspace_bytes(g, 1, len(rec)), dtype=torch.uint8, device=dev)
         recb = torch.empty((nt, len(rec)), dtype=torch.float32, device=dev)
         wave.forward(g, vel, wav, src, rec, workspace=ws, rec_out=recb)
@@ -277,14 +280,15 @@ def reduced_precision_leg(dev):
 
 def two_step_leg(dev):
     """Temporal blocking: the forward solve with two fused leapfrog steps per launch
-    (64-plane z-chunks) against one step per launch, on the sweep's 256^3 workload and
-    at 512^3 (FP32; 20 algorithmic bytes per point per two-step launch)."""
+    (the library's z-chunks: 64 planes, 128 at SO8 where that still gives 512
+    workgroups) against one step per launch, on the sweep's 256^3 workload and at
+    512^3 (FP32; 20 algorithmic bytes per point per two-step launch)."""
     from paper_1912_00695_amd import wave
     res = {}
     for n, so, nt in ((256, 4, 500), (256, 8, 500), (512, 2, 100), (512, 4, 100), (512, 6, 100),
                       (512, 8, 100)):
         item = {}
-        for name, path, zc in (("two_step", wave.PATH_TWO_STEP, 64),
+        for name, path, zc in (("two_step", wave.PATH_TWO_STEP, 0),
                                ("one_step", wave.PATH_ONE_STEP, 0)):
             S = Solver(c2_problem(so, nt=nt, n=(n, n, n), path=path, zchunk=zc), dev)
             e, _ = time_solves(S, 2, 1)
@@ -293,8 +297,8 @@ def two_step_leg(dev):
         item["speedup"] = round(item["two_step_gpts"] / item["one_step_gpts"], 3)
         res["%d^3_so%d" % (n, so)] = item
         log("two-step %d^3 SO%d: %s" % (n, so, item))
-    res["default"] = ("two-step kernel used by default (64-plane z-chunks) for SO2 from 3e7, "
-                      "SO4 from 6e7 and SO6 from 8e7 grid points")
+    res["default"] = ("two-step kernel used by default for SO2 from 3e7, SO4 from 6e7, SO6 "
+                      "from 8e7 and SO8 from 1.2e8 grid points")
     return res
 
 
@@ -384,34 +388,45 @@ def adjoint_gradient_leg(dev):
     return res
 
 
-def serving_saturated_leg(dev, count=40):
+def serving_saturated_leg(dev, count=40, reps=3):
     """The first `count` requests of a seeded serving mix submitted at once (saturated
-    engine), against the same shots solved one by one with wave_forward."""
+    engine), against the same shots solved one by one with wave_forward; `reps`
+    interleaved runs of each (a run's throughput varies by several per cent with the
+    host's timing of submissions and uploads), medians reported."""
     import numpy as np
     import torch
     from paper_1912_00695_amd import serving, wave
-    rng = np.random.default_rng(6)
-    reqs = [serving.mixed_request(rng) for _ in range(count)]
-    upd = sum(r["updates"] for r in reqs)
-    with serving.Engine(96 << 30, 64) as eng:
+
+    def requests():
+        rng = np.random.default_rng(6)
+        return [serving.mixed_request(rng) for _ in range(count)]
+
+    upd = sum(r["updates"] for r in requests())
+    batched, plain, builds = [], [], []
+    for _ in range(reps):
+        reqs = requests()
+        with serving.Engine(96 << 30, 64) as eng:
+            t0 = time.perf_counter()
+            for r in reqs:
+                eng.submit(r["grid"], r["vel"], r["wavelet"], r["src"], r["rec"])
+            eng.drain(900)
+            batched.append(upd / (time.perf_counter() - t0) / 1e9)
+            builds.append(eng.stats()["graph_builds"])
+        reqs = requests()
+        torch.cuda.synchronize()
         t0 = time.perf_counter()
         for r in reqs:
-            eng.submit(r["grid"], r["vel"], r["wavelet"], r["src"], r["rec"])
-        eng.drain(900)
-        t_batched = time.perf_counter() - t0
-        st = eng.stats()
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    for r in reqs:
-        wave.forward(r["grid"], torch.from_numpy(r["vel"]).to(dev),
-                     torch.from_numpy(r["wavelet"]).to(dev), r["src"], r["rec"])["rec"].cpu()
-    torch.cuda.synchronize()
-    t_plain = time.perf_counter() - t0
-    res = {"requests": count, "batched_gpts": round(upd / t_batched / 1e9, 2),
-           "plain_sequential_gpts": round(upd / t_plain / 1e9, 2),
-           "speedup": round(t_plain / t_batched, 3), "graph_builds": st["graph_builds"],
-           "note": "same requests, bitwise-identical results; both include host->device "
-                   "upload of each request's inputs"}
+            wave.forward(r["grid"], torch.from_numpy(r["vel"]).to(dev),
+                         torch.from_numpy(r["wavelet"]).to(dev), r["src"], r["rec"])["rec"].cpu()
+        torch.cuda.synchronize()
+        plain.append(upd / (time.perf_counter() - t0) / 1e9)
+    mb, mp = float(np.median(batched)), float(np.median(plain))
+    res = {"requests": count, "runs": reps, "batched_gpts": round(mb, 2),
+           "plain_sequential_gpts": round(mp, 2), "speedup": round(mb / mp, 3),
+           "batched_runs_gpts": [round(v, 1) for v in batched],
+           "plain_runs_gpts": [round(v, 1) for v in plain], "graph_builds": builds,
+           "note": "medians of interleaved runs; same requests, bitwise-identical results; "
+                   "both include host->device upload of each request's inputs"}
     log("serving saturated: %s" % res)
     return res
 
@@ -524,6 +539,9 @@ def main():
     ap.add_argument("--launch", default="default", choices=["default", "direct", "graph"],
                     help="launch policy of the timed solves (default: graph replay of "
                          "repeated calls)")
+    ap.add_argument("--kernel", default="default", choices=["default", "one_step", "two_step"],
+                    help="kernel family of the timed solve (default: the library's choice, "
+                         "the one-step kernel at 256^3)")
     ap.add_argument("--no-sweep", action="store_true")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-serving", action="store_true")
@@ -554,6 +572,8 @@ def main():
         sys.exit(2)
     from paper_1912_00695_amd import wave as _w
     launch_path = {"default": 0, "direct": _w.PATH_DIRECT, "graph": _w.PATH_GRAPH}[args.launch]
+    launch_path |= {"default": 0, "one_step": _w.PATH_ONE_STEP,
+                    "two_step": _w.PATH_TWO_STEP}[args.kernel]
     P = c2_problem(args.so, nt=args.nt, n=(args.n,) * 3, path=launch_path)
     solver = Solver(P, dev)
     log("timing %d solves of %d^3 SO%d x %d steps (warmup %d)" % (args.steps, args.n, args.so,
@@ -622,17 +642,21 @@ def main():
             log("sweep SO%d: %.2f Gpt/s" % (so, g))
             del S
         out["so_sweep_256"] = sweep
-        # cache-defeating control: 512^3 (4 fields x 537 MB per step, far above the
-        # 256 MB Infinity Cache)
-        P5 = c2_problem(8, nt=500, n=(512, 512, 512))
-        S = Solver(P5, dev)
-        e, _ = time_solves(S, 2, 0)
-        g = 512 ** 3 * 500 * 2 / e / 1e9
-        out["control_512_so8"] = {"gpts": round(g, 2),
-                                  "hbm_frac": round(g * ALG_BYTES_PER_PT / HBM_PEAK_GBS, 4),
-                                  "nt": 500}
-        log("control 512^3 SO8: %.2f Gpt/s" % g)
-        del S
+        # cache-defeating control: the one-step kernel at 512^3 (4 fields x 537 MB per
+        # step, far above the 256 MB Infinity Cache); the library's default path there
+        # is the two-step kernel, timed beside it
+        from paper_1912_00695_amd import wave as _w5
+        ctl = {}
+        for key, path in (("gpts", _w5.PATH_ONE_STEP), ("default_path_gpts", 0)):
+            S = Solver(c2_problem(8, nt=500, n=(512, 512, 512), path=path), dev)
+            e, _ = time_solves(S, 2, 0)
+            ctl[key] = round(512 ** 3 * 500 * 2 / e / 1e9, 2)
+            del S
+        out["control_512_so8"] = {"gpts": ctl["gpts"], "kernel": "step_kernel<4,false> (one step)",
+                                  "hbm_frac": round(ctl["gpts"] * ALG_BYTES_PER_PT / HBM_PEAK_GBS, 4),
+                                  "nt": 500, "default_path_gpts": ctl["default_path_gpts"],
+                                  "default_path": "two-step kernel, 128-plane chunks"}
+        log("control 512^3 SO8: %s" % out["control_512_so8"])
     if not args.no_sweep:
         out["small_grids"] = small_grid_leg(dev)
         out["lowp_512_so8"] = reduced_precision_leg(dev)

@@ -354,21 +354,33 @@ bool fused_tiling_ok(const Ctx& C) { return C.L.fused && C.T.zchunk >= C.g->so; 
 // the one-step kernel with its default tiling): SO2 +2 % at 320^3, +0 % at 384^3,
 // +22 % at 448^3, +34 % at 512^3; SO4 -15 % at 256^3, -4 % at 320^3, -6 % at 384^3,
 // +14 % at 448^3, +23 % at 512^3; SO6 -11 % at 320^3, -14 % at 384^3, +6 % at 448^3,
-// +11 % at 512^3; SO8 (158 registers per lane, one 512-thread workgroup per CU) -10 %
-// at 512^3. Below these sizes the one-step kernel's working set is largely served by
+// +11 % at 512^3. SO8 runs on tiles twice as tall (one 768-thread workgroup per
+// CU): +5 % at 512^3 with 128-plane chunks (512 workgroups; 64-plane chunks +2 %,
+// 32-plane -7 %), -2 % at 448^3 (64-plane chunks: 128 would leave 392 workgroups,
+// -18 %). Below these sizes the one-step kernel's working set is largely served by
 // the 256 MiB Infinity Cache; longer two-step chunks (128, 256 planes) lost at
-// SO2/SO4. Chosen by the library: radius r <= 3 and at least kFusedMinPoints[r] grid
-// points. WAVE_PATH_TWO_STEP asks for it at radius <= 4, WAVE_PATH_ONE_STEP never
-// takes it; its z-chunks are the grid's zchunk, else kFusedZChunk planes.
-constexpr int64_t kFusedMinPoints[4] = {0, 30000000, 60000000, 80000000};
+// SO2/SO4/SO6. Chosen by the library: at least kFusedMinPoints[r] grid points.
+// WAVE_PATH_TWO_STEP asks for it at radius <= 4, WAVE_PATH_ONE_STEP never takes it;
+// its z-chunks are the grid's zchunk, else fused_zchunk's.
+constexpr int64_t kFusedMinPoints[5] = {0, 30000000, 60000000, 80000000, 120000000};
 constexpr int kFusedZChunk = 64;
+int fused_zchunk(const wave_grid* g) {
+  const int r = g->so / 2;
+  if (r == 4) {  // 128-plane chunks where they still give 512 workgroups or more
+    const int64_t tiles = (int64_t)((g->nx + TX - 1) / TX) *
+                          ((g->ny + f2_tiles_y(r) * TY - 1) / (f2_tiles_y(r) * TY)) *
+                          ((g->nz + 127) / 128);
+    if (tiles >= 512) return 128;
+  }
+  return kFusedZChunk;
+}
 bool want_fused(const wave_grid* g, int* zchunk) {
-  *zchunk = g->zchunk > 0 ? g->zchunk : kFusedZChunk;
+  *zchunk = g->zchunk > 0 ? g->zchunk : fused_zchunk(g);
   if (store_kind(g) != WAVE_STORE_F32 || g->so / 2 > 4) return false;
   if (g->path & WAVE_PATH_ONE_STEP) return false;
   if (g->path & WAVE_PATH_TWO_STEP) return true;
   const int64_t npts = (int64_t)g->nx * g->ny * g->nz;
-  return g->so / 2 <= 3 && npts >= kFusedMinPoints[g->so / 2];
+  return npts >= kFusedMinPoints[g->so / 2];
 }
 
 // Source tables of the two-step kernel: for every two-step tile (f2_tiles_y(r)
