@@ -100,6 +100,7 @@ struct Shot {
   int counter = 0;
   int status = WAVE_EAGAIN;
   int zchunk = 0;  // z-chunk length chosen at admission
+  int cnt0[2] = {0, 0};  // initial step counters (upload source)
   double t_submit = 0, t_admit = 0, t_done = 0;
 };
 
@@ -119,6 +120,7 @@ class Engine {
     HIP_TRY(hipGetDevice(&device_));
     HIP_TRY(hipMalloc(&pool_, budget_));
     HIP_TRY(hipMalloc(&d_desc_, sizeof(ShotDesc) * max_slots_));
+    HIP_TRY(hipMalloc(&d_cnt_, sizeof(int) * 2 * max_slots_));
     table_cap_ = 1 << 20;
     for (int k = 0; k < 2; ++k) HIP_TRY(hipMalloc(&d_table_[k], sizeof(BatchEntry) * table_cap_));
     HIP_TRY(hipMalloc(&d_slots_, sizeof(int) * max_slots_));
@@ -159,6 +161,7 @@ class Engine {
     for (int k = 0; k < 2; ++k)
       if (d_table_[k]) (void)hipFree(d_table_[k]);
     if (d_desc_) (void)hipFree(d_desc_);
+    if (d_cnt_) (void)hipFree(d_cnt_);
     if (pool_) (void)hipFree(pool_);
   }
 
@@ -385,7 +388,7 @@ class Engine {
       // (the active set can shrink between rebuilds: finished shots stay in the graph)
       const int ng = (int)graph_shots_.size();
       if (!launched ||
-          launch_gather_counters(d_desc_, d_slots_, ng, d_counts_, s_exec_) != hipSuccess ||
+          launch_gather_counters(d_cnt_, d_slots_, ng, d_counts_, s_exec_) != hipSuccess ||
           hipMemcpyAsync(h_counts_, d_counts_, sizeof(int) * ng, hipMemcpyDeviceToHost,
                          s_exec_) != hipSuccess ||
           hipStreamSynchronize(s_exec_) != hipSuccess) {
@@ -498,10 +501,10 @@ class Engine {
     d.nsrc = s->nsrc;
     d.nrec = s->nrec;
     d.nt = g->nt;
-    d.cnt[0] = 0;
-    d.cnt[1] = 0;
     s->nsamp_blocks = s->nrec > 0 ? (s->nrec + NTHREADS - 1) / NTHREADS : 0;
     HIP_TRY(hipMemcpyAsync(d_desc_ + s->slot, &s->desc, sizeof(ShotDesc), hipMemcpyHostToDevice,
+                           s_up_));
+    HIP_TRY(hipMemcpyAsync(d_cnt_ + 2 * s->slot, s->cnt0, sizeof(s->cnt0), hipMemcpyHostToDevice,
                            s_up_));
     HIP_TRY(hipEventCreateWithFlags(&s->ready, hipEventDisableTiming));
     HIP_TRY(hipEventRecord(s->ready, s_up_));
@@ -559,7 +562,7 @@ class Engine {
     hipError_t err = hipSuccess;
     for (auto& sg : segs)
       for (int k = 0; k < kReplaySteps && err == hipSuccess; ++k)
-        err = launch_batched(d_desc_, tab + sg.second.first, sg.second.second, sg.first, k & 1,
+        err = launch_batched(d_desc_, d_cnt_, tab + sg.second.first, sg.second.second, sg.first, k & 1,
                              s_exec_);
     hipError_t e2 = hipStreamEndCapture(s_exec_, &graph);
     if (err != hipSuccess || e2 != hipSuccess) {
@@ -635,6 +638,7 @@ class Engine {
   PoolAlloc alloc_;
   size_t pool_used_ = 0, max_pool_bytes_ = 0;
   ShotDesc* d_desc_ = nullptr;
+  int* d_cnt_ = nullptr;  // step counters, two per slot (cnts[2 * slot + parity])
   BatchEntry* d_table_[2] = {nullptr, nullptr};
   int table_cap_ = 0, cur_table_ = 0;
   int* d_slots_ = nullptr;

@@ -138,8 +138,10 @@ struct ShotDesc {
   const float* wavelet;    // [nt][nsrc]
   float* traces;           // [nt][nrec]
   int nsrc, nrec, nt;
-  int cnt[2];              // step counter, parity-indexed (see batched_step_kernel)
 };
+// The engine's step counters live beside the descriptors, two per slot
+// (cnts[2 * slot + parity], see batched_step_kernel): the descriptors stay
+// read-only in the kernel, so its arguments can be held like kernel arguments.
 struct BatchEntry {
   int shot;   // slot in the descriptor array
   int tile;   // stencil tile id >= 0, or -1-k for sampling block k
@@ -156,10 +158,10 @@ hipError_t launch_step_basic(const StepArgs& a, int r, hipStream_t s);
 // two fused steps (radius r <= 4); nt: non-temporal stores of the two outputs
 hipError_t launch_fused2(const Fused2Args& f, int r, bool nt, hipStream_t s);
 // one batched step of every shot in table (space-order radius r, launch parity)
-hipError_t launch_batched(ShotDesc* shots, const BatchEntry* table, int nentries, int r,
+hipError_t launch_batched(const ShotDesc* shots, int* cnts, const BatchEntry* table, int nentries, int r,
                           int parity, hipStream_t s);
 // out[i] = shots[slots[i]].cnt[0]
-hipError_t launch_gather_counters(const ShotDesc* shots, const int* slots, int n, int* out,
+hipError_t launch_gather_counters(const int* cnts, const int* slots, int n, int* out,
                                   hipStream_t s);
 // out[i] = sum_c w[8i+c] field[idx[8i+c]], the field decoded with level m's scale
 hipError_t launch_sample(const void* field, int st, LevelMeta meta, int m, const int* idx,
