@@ -229,17 +229,22 @@ bool points_ok(const wave_grid* g, const double* xyz, int np) {
 }
 
 
+// Injection tables in "column" order, independent of the z-chunking: a column is
+// one xy tile (TX x TY points) on one plane, numbered (xy tile) * nz + z with xy
+// tile = ty * ntile_x + tx; tile_beg[c] is the first entry of column c, so the
+// entries of xy tile xy on planes [z0, z1) are tile_beg[xy nz + z0] ..
+// tile_beg[xy nz + z1], for any chunk a kernel is given.
 void build_point_tables(const wave_grid* g, const Geom& G, const Tiling& T, const double* xyz,
                         int np, const PointTables& P, Blob& B) {
   int* tile_beg = B.at<int>(P.tile_beg);
-  const int ntiles = T.nblocks;
+  const int ntiles = T.ntile_x * T.ntile_y * G.nz;  // columns
   std::fill(tile_beg, tile_beg + ntiles + 1, 0);
-  // One term per (point, trilinear corner) in point order: the corner's tile, plane
-  // and local index in the tile, the point and the weight. A stable counting sort
-  // by tile, then a stable sort of each tile's terms by plane and local index
-  // (skipped where they are in that order already, as for points given in raster
-  // order on a grid plane), puts the terms of one grid point together in point
-  // order, the order in which the kernels sum them.
+  // One term per (point, trilinear corner) in point order: the corner's column and
+  // local index in the tile, the point and the weight. A stable counting sort by
+  // column, then a stable sort of each column's terms by local index (skipped where
+  // they are in that order already, as for points given in raster order on a grid
+  // plane), puts the terms of one grid point together in point order, the order in
+  // which the kernels sum them.
   struct Term {
     int tile, z, local, p;
     float w;
@@ -261,7 +266,7 @@ void build_point_tables(const wave_grid* g, const Geom& G, const Tiling& T, cons
       const int i = ijk[3 * k], j = ijk[3 * k + 1], z = ijk[3 * k + 2];
       sidx[8 * p + k] = (int)((int64_t)z * G.plane + (int64_t)j * G.pitch + i);
       sw[8 * p + k] = (float)w[k];
-      const int tile = ((z / T.zchunk) * T.ntile_y + j / TY) * T.ntile_x + i / TX;
+      const int tile = ((j / TY) * T.ntile_x + i / TX) * G.nz + z;
       terms.push_back(Term{tile, z, (j % TY) * TX + (i % TX), p, (float)w[k]});
       ++cnt[(size_t)tile + 1];
     }
@@ -273,35 +278,22 @@ void build_point_tables(const wave_grid* g, const Geom& G, const Tiling& T, cons
     for (const Term& q : terms) sorted[pos[q.tile]++] = q;
   }
   std::vector<Term>().swap(terms);
-  const auto by_plane = [](const Term& a, const Term& b) {
-    return a.z != b.z ? a.z < b.z : a.local < b.local;
-  };
-  // A tile whose terms span a few planes (points off a grid plane touch two) is
-  // ordered by a stable counting sort on (plane, index in the tile) in cache; wider
-  // spans by a stable comparison sort.
+  // All terms of a column lie on one plane; each column is ordered by a stable
+  // counting sort on the index in the tile (in cache).
+  const auto by_local = [](const Term& a, const Term& b) { return a.local < b.local; };
   std::vector<Term> tmp;
   std::vector<int> pos;
   for (int t = 0; t < ntiles; ++t) {
     const auto b0 = sorted.begin() + cnt[t], b1 = sorted.begin() + cnt[(size_t)t + 1];
-    if (b1 - b0 <= 1 || std::is_sorted(b0, b1, by_plane)) continue;
-    int zlo = b0->z, zhi = b0->z;
-    for (auto it = b0; it != b1; ++it) {
-      zlo = std::min(zlo, it->z);
-      zhi = std::max(zhi, it->z);
-    }
-    if (zhi - zlo >= 4) {
-      std::stable_sort(b0, b1, by_plane);
-      continue;
-    }
-    const int nkey = (zhi - zlo + 1) * TX * TY;
-    pos.assign((size_t)nkey + 1, 0);
-    for (auto it = b0; it != b1; ++it) ++pos[(size_t)(it->z - zlo) * TX * TY + it->local + 1];
-    for (int k = 0; k < nkey; ++k) pos[(size_t)k + 1] += pos[k];
+    if (b1 - b0 <= 1 || std::is_sorted(b0, b1, by_local)) continue;
+    pos.assign((size_t)TX * TY + 1, 0);
+    for (auto it = b0; it != b1; ++it) ++pos[(size_t)it->local + 1];
+    for (int k = 0; k < TX * TY; ++k) pos[(size_t)k + 1] += pos[k];
     tmp.resize(b1 - b0);
-    for (auto it = b0; it != b1; ++it) tmp[pos[(size_t)(it->z - zlo) * TX * TY + it->local]++] = *it;
+    for (auto it = b0; it != b1; ++it) tmp[pos[(size_t)it->local]++] = *it;
     std::copy(tmp.begin(), tmp.end(), b0);
   }
-  // one entry per distinct (tile, plane, local index), its terms in CSR order
+  // one entry per distinct (column, local index), its terms in CSR order
   InjEntry* ent = B.at<InjEntry>(P.ent);
   int* cidx = B.at<int>(P.csr_idx);
   float* cw = B.at<float>(P.csr_w);
@@ -327,16 +319,9 @@ void build_point_tables(const wave_grid* g, const Geom& G, const Tiling& T, cons
     a = b;
   }
   for (int t = 0; t < ntiles; ++t) tile_beg[t + 1] += tile_beg[t];
-  // group ends: first entry of the next plane group within each tile
-  for (int t = 0; t < ntiles; ++t) {
-    int b = tile_beg[t], end = tile_beg[t + 1];
-    while (b < end) {
-      int q = b;
-      while (q < end && ent[q].z == ent[b].z) ++q;
-      for (int k = b; k < q; ++k) ent[k].grp_end = q;
-      b = q;
-    }
-  }
+  // group ends: a plane's group is its column
+  for (int t = 0; t < ntiles; ++t)
+    for (int k = tile_beg[t]; k < tile_beg[t + 1]; ++k) ent[k].grp_end = tile_beg[t + 1];
   B.mark(P.tile_beg, ((size_t)ntiles + 1) * sizeof(int));
   B.mark(P.ent, (size_t)e * sizeof(InjEntry));
   B.mark(P.csr_idx, nterm * sizeof(int));

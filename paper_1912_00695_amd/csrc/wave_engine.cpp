@@ -48,24 +48,15 @@ constexpr int kReplaySteps = 16;    // launches per group in one captured graph 
 constexpr double kSyncWork = 2e-3;  // GPU seconds of work between host syncs while shots wait
 constexpr double kSyncWorkIdle = 10e-3;  // ... and while none waits
 constexpr double kUpdateRate = 250e9;  // grid-point updates per second, for that estimate
-// z-chunk length of a resident shot (unless its grid fixes one), chosen at
-// admission. A shot admitted into an idle engine (nothing else resident or
-// waiting) will most likely be stepped alone in its cache group: it gets enough
-// chunks for about 512 workgroups (a group of one mid-sized shot with 32-plane
-// chunks leaves CUs with one workgroup or none: 192^3 SO8 ran 29 us per step with
-// 32-plane chunks, 217 workgroups, against 20.6 with 14-plane chunks), at least 8
-// planes and at most 32. Shots admitted while others are resident or waiting share
-// groups, where long chunks re-read fewer priming planes: 32. Measured on the
-// saturated serving mix (40 requests at once, 4 runs): 314 Gpt/s median with 32
-// planes for every shot against 297 with the fill rule for every shot; on a
-// 300-request Poisson stream at 20/s the fill rule gave p50 / p99 latency 14.9 / 64.5
-// ms against 22.1 / 79.5.
-constexpr int kEngineZChunk = 32;
-int engine_fill_zchunk(const wave_grid* g) {
-  const int bxy = ((g->nx + TX - 1) / TX) * ((g->ny + TY - 1) / TY);
-  const int nch = std::max(1, 512 / bxy);
-  return std::min(kEngineZChunk, std::max(8, (g->nz + nch - 1) / nch));
-}
+// z-chunk length of a cache group's shots, chosen when the group's table is built
+// (the injection tables do not depend on it): the longest of 32, 24, ..., 1 planes
+// that gives the group at least 512 stencil workgroups (a grid that fixes its
+// zchunk keeps it). A group of one mid-sized shot gets short chunks that fill the
+// GPU (192^3 SO8 alone: 32-plane chunks, 217 workgroups, ran 29 us per step against
+// 20.6 with 14-plane chunks); a group of several shots keeps long chunks, which
+// re-read fewer planes to prime their queues.
+constexpr int kChunkLens[] = {32, 24, 16, 12, 8, 6, 4, 3, 2, 1};
+constexpr int kEngineZChunk = 32;  // tiling of a shot's context (tables are chunk-free)
 // Shots stepped together in one run of kReplaySteps launches: their per-step arrays
 // (two levels and v^2 dt^2) fit the 256 MB Infinity Cache together, so they stay
 // cache-resident across the run's steps. wave_engine_set_group_bytes overrides.
@@ -99,8 +90,8 @@ struct Shot {
   std::atomic<int> state{QUEUED};
   int counter = 0;
   int status = WAVE_EAGAIN;
-  int zchunk = 0;  // z-chunk length chosen at admission
   int cnt0[2] = {0, 0};  // initial step counters (upload source)
+  size_t entries = 0;    // its workgroups in the current graph's table
   double t_submit = 0, t_admit = 0, t_done = 0;
 };
 
@@ -294,13 +285,8 @@ class Engine {
         std::vector<size_t> qb;
         for (Shot* s : queue_) qb.push_back(s->bytes);
         const std::vector<sched::Admission> adm = sched::admit(qb, alloc_, nfree);
-        // an engine with nothing resident and a single request waiting is idle
-        const bool idle = resident_ == 0 && queue_.size() == 1;
         for (const sched::Admission& ad : adm) {
           Shot* s = queue_[ad.pos];
-          s->zchunk = s->g.zchunk > 0 ? s->g.zchunk
-                      : idle          ? engine_fill_zchunk(&s->g)
-                                      : kEngineZChunk;
           const int slot = free_slot();
           s->off = ad.off;
           s->slot = slot;
@@ -421,7 +407,7 @@ class Engine {
       }
       // idle workgroups of finished shots: rebuild once they are a quarter of a launch
       size_t idle_entries = 0;
-      for (Shot* s : finished) idle_entries += (size_t)s->C.T.nblocks + s->nsamp_blocks;
+      for (Shot* s : finished) idle_entries += s->entries;
       if (!finished.empty() && (waiting || !any_active || 4 * idle_entries > graph_entries_)) {
         for (Shot* s : finished) release(s);
         finished.clear();
@@ -468,9 +454,10 @@ class Engine {
   int start_upload(Shot* s) {
     char* base = static_cast<char*>(pool_) + s->off;
     const wave_grid* g = &s->g;
-    // z-chunks as chosen at admission; the values do not depend on the chunking
+    // the launch's chunking is chosen per cache group (rebuild_graph); the tables
+    // and the values do not depend on it
     int st = init_ctx(s->C, g, s->nsrc, s->nrec, WAVE_MODE_FORWARD, 0, base, s->bytes, s_up_,
-                      s->zchunk, false);
+                      kEngineZChunk, false);
     if (st) return st;
     s->C.g = &s->g;
     s->off_wav = s->C.L.total;
@@ -521,6 +508,7 @@ class Engine {
     struct Group {
       int r;
       size_t bytes;
+      std::vector<Shot*> shots;
       std::vector<BatchEntry> e;
     };
     const size_t gb = group_bytes_.load();
@@ -538,8 +526,33 @@ class Engine {
       if (gi == groups.size()) groups.push_back(Group{r, 0, {}});
       Group& G = groups[gi];
       G.bytes += b;
-      for (int t = 0; t < s->C.T.nblocks; ++t) G.e.push_back(BatchEntry{s->slot, t});
-      for (int k = 0; k < s->nsamp_blocks; ++k) G.e.push_back(BatchEntry{s->slot, -1 - k});
+      G.shots.push_back(s);
+    }
+    for (Group& G : groups) {
+      int zc = 1;
+      for (const int len : kChunkLens) {
+        int64_t wg = 0;
+        for (const Shot* s : G.shots) {
+          const int z = s->g.zchunk > 0 ? s->g.zchunk : len;
+          wg += (int64_t)s->C.T.ntile_x * s->C.T.ntile_y * ((s->g.nz + z - 1) / z);
+        }
+        if (wg >= 512) {
+          zc = len;
+          break;
+        }
+      }
+      // per shot: its stencil blocks chunk-major (the single-solve tile order), then
+      // its sampling blocks
+      for (Shot* s : G.shots) {
+        const int z = s->g.zchunk > 0 ? s->g.zchunk : zc;
+        const int bxy = s->C.T.ntile_x * s->C.T.ntile_y;
+        const size_t e0 = G.e.size();
+        for (int z0 = 0; z0 < s->g.nz; z0 += z)
+          for (int xy = 0; xy < bxy; ++xy)
+            G.e.push_back(BatchEntry{s->slot, xy, z0, std::min(z0 + z, s->g.nz)});
+        for (int k = 0; k < s->nsamp_blocks; ++k) G.e.push_back(BatchEntry{s->slot, -1 - k, 0, 0});
+        s->entries = G.e.size() - e0;
+      }
     }
     std::vector<BatchEntry> all;
     std::vector<std::pair<int, std::pair<int, int>>> segs;  // radius, (offset, count)

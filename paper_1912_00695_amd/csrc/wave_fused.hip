@@ -174,10 +174,10 @@ __device__ __forceinline__ void fused2_tile(const Fused2Args& f, const int t) {
     ezb[k] = INT_MAX;
     egb[k] = 0;
     const int ty1 = K * ty_t + k;
-    if (a.tile_beg != nullptr && ty1 < f.ntile_y1) {
-      const int t1 = (zc * f.ntile_y1 + ty1) * a.ntile_x + tx_t;
-      eb[k] = a.tile_beg[t1];
-      eb_end[k] = a.tile_beg[t1 + 1];
+    if (a.tile_beg != nullptr && ty1 < f.ntile_y1) {  // column tables of xy tile xy1
+      const int xy1 = ty1 * a.ntile_x + tx_t;
+      eb[k] = a.tile_beg[xy1 * nz + z0];
+      eb_end[k] = a.tile_beg[xy1 * nz + z1];
       if (eb[k] < eb_end[k]) {
         ezb[k] = a.ent[eb[k]].z;
         egb[k] = a.ent[eb[k]].grp_end;

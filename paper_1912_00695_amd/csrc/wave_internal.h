@@ -34,7 +34,7 @@ struct InjEntry {
   int local;    // (j - tile_y) * TX + (i - tile_x)
   int csr_beg;  // terms [csr_beg, csr_end)
   int csr_end;
-  int grp_end;  // first entry of the next plane group in this tile
+  int grp_end;  // end of the run of entries on this entry's plane (in its tile)
   int tidx;     // an entry with a single term: its trace index (else -1)
   float w;      //   and its weight
   int pad;
@@ -84,8 +84,11 @@ struct StepArgs {
   float wx[MAXR + 1], wy[MAXR + 1], wz[MAXR + 1];
   float wc;
   float dt;           // time step (the unfactorised ablation kernel only)
-  // fused injection into `out`: per-tile entry lists
-  const int* tile_beg;         // [ntiles + 1]
+  // fused injection into `out`: entry lists per column (xy tile, plane), numbered
+  // (ty * ntile_x + tx) * nz + z; tile_beg[c] is column c's first entry, so a
+  // workgroup's planes [z0, z1) of xy tile xy are entries tile_beg[xy nz + z0] ..
+  // tile_beg[xy nz + z1] whatever the chunking
+  const int* tile_beg;         // [ntile_x * ntile_y * nz + 1]
   const InjEntry* ent;
   const int* csr_idx;          // trace index
   const float* csr_w;          // weight
@@ -144,7 +147,8 @@ struct ShotDesc {
 // read-only in the kernel, so its arguments can be held like kernel arguments.
 struct BatchEntry {
   int shot;   // slot in the descriptor array
-  int tile;   // stencil tile id >= 0, or -1-k for sampling block k
+  int xy;     // xy tile ty * ntile_x + tx of a stencil block, or -1-k for sampling block k
+  int z0, z1; // the stencil block's planes [z0, z1) (at most MAXZCHUNK)
 };
 
 // Launchers (wave_kernels.hip). All return hipGetLastError() after the launch.

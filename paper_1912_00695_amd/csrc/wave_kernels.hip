@@ -64,13 +64,14 @@ constexpr bool zunroll4(int r) { return ((WAVE_ZUNROLL4_MASK) >> r) & 1; }
 constexpr bool bstore(int r) { return ((WAVE_BSTORE_MASK) >> r) & 1; }
 constexpr bool halo_ring(int r) { return ((WAVE_HRING_MASK) >> r) & 1; }
 
-// One tile of one step: the z-sweep of a TX x TY column block over one z-chunk.
-// Shared by the single-shot kernel and the batched serving kernel, so a shot's
-// values do not depend on what else is in the launch.
+// One tile of one step: the z-sweep of the TX x TY column block xy (= ty *
+// ntile_x + tx) over planes [z0, z1). Shared by the single-shot kernel and the
+// batched serving kernel, so a shot's values do not depend on what else is in the
+// launch or on how its planes are chunked.
 template <int R, bool GRAD, int ST, bool DIFF, bool NT, bool BASIC = false>
-__device__ __forceinline__ void step_tile(const StepArgs& a, const int t, const float dec_c,
-                                          const float dec_p, const float enc_u,
-                                          const float enc_d) {
+__device__ __forceinline__ void step_tile(const StepArgs& a, const int xy, const int z0,
+                                          const int z1, const float dec_c, const float dec_p,
+                                          const float enc_u, const float enc_d) {
   constexpr int XH = R <= 4 ? 4 : (R <= 8 ? 8 : 12);  // x-halo width (multiple of 4)
   constexpr int XH4 = XH / 4;
   constexpr int LROW4 = NTX + 2 * XH4;  // float4 per LDS row
@@ -97,15 +98,11 @@ __device__ __forceinline__ void step_tile(const StepArgs& a, const int t, const 
   __shared__ Raw hbuf[HRG ? R + 1 : 1][HRG ? NH : 1];
   const auto hslot = [](const int p) { return p % (R + 1); };  // p >= 0
 
-  const int tx_t = t % a.ntile_x;
-  const int rest = t / a.ntile_x;
-  const int ty_t = rest % a.ntile_y;
-  const int zc = rest / a.ntile_y;
+  const int tx_t = xy % a.ntile_x;
+  const int ty_t = xy / a.ntile_x;
   const int xt = tx_t * TX, yt = ty_t * TY;
   const int nx = a.g.nx, ny = a.g.ny, nz = a.g.nz;
   const int64_t plane = a.g.plane;
-  const int z0 = zc * a.zchunk;
-  const int z1 = min(z0 + a.zchunk, nz);
   const int tid = threadIdx.x;
   const int tx = tid % NTX, ty = tid / NTX;
   const int x0 = xt + tx * VX, y = yt + ty;
@@ -232,8 +229,8 @@ __device__ __forceinline__ void step_tile(const StepArgs& a, const int t, const 
   int e = 0, e_end = 0, ez = INT_MAX, eg = 0;  // eg: end of the group at plane ez
   const auto* ent = gmem(a.ent);
   if (a.tile_beg != nullptr) {
-    e = gmem(a.tile_beg)[t];
-    e_end = gmem(a.tile_beg)[t + 1];
+    e = gmem(a.tile_beg)[xy * nz + z0];
+    e_end = gmem(a.tile_beg)[xy * nz + z1];
     if (e < e_end) {
       ez = ent[e].z;
       eg = ent[e].grp_end;
@@ -562,13 +559,18 @@ __global__ void __launch_bounds__(NTHREADS) step_kernel(const StepArgs a) {
       a.samp_out[r] = sample_point<ST>(a.cur, dec_c, a.samp_idx, a.samp_w, r);
     return;
   }
+  // logical tile t = (chunk * ntile_y + ty) * ntile_x + tx
   const int t = a.xcd_remap ? remap_tile(bid, a.nstencil_blocks) : bid;
-  step_tile<R, GRAD, ST, DIFF, NT, BASIC>(a, t, dec_c, dec_p, enc_u, enc_d);
+  const int bxy = a.ntile_x * a.ntile_y;
+  const int z0 = (t / bxy) * a.zchunk;
+  step_tile<R, GRAD, ST, DIFF, NT, BASIC>(a, t % bxy, z0, min(z0 + a.zchunk, a.g.nz), dec_c, dec_p,
+                                          enc_u, enc_d);
 }
 
 // Serving: one launch advances every active shot of one space order by a step.
-// Block b (after the XCD remap) takes table entry b = (shot, tile); tile < 0 is
-// sampling block -1-tile of that shot. The shot's step n is read from its
+// Block b (after the XCD remap) takes table entry b = (shot, xy tile, planes
+// [z0, z1)); xy < 0 is sampling block -1-xy of that shot (the host chooses each
+// group's chunking when it builds the table). The shot's step n is read from its
 // parity-indexed counter cnts[2 * shot + parity] (launches alternate parity), so
 // the same captured launch sequence replays for any mix of shots at any steps. A
 // shot whose n reached nt only samples its last level; past nt it does nothing.
@@ -586,7 +588,8 @@ __global__ void __launch_bounds__(NTHREADS) batched_step_kernel(const ShotDesc* 
   const ShotDesc* sd = shots + e.shot;
   const int n = cnts[2 * e.shot + parity];
   const int nt = sd->nt;
-  if (e.tile == 0 && threadIdx.x == 0) cnts[2 * e.shot + (parity ^ 1)] = n <= nt ? n + 1 : n;
+  if (e.xy == 0 && e.z0 == 0 && threadIdx.x == 0)  // the shot's first stencil block
+    cnts[2 * e.shot + (parity ^ 1)] = n <= nt ? n + 1 : n;
   if (n > nt) return;
   StepArgs a = sd->a;
   a.cur = sd->buf[n & 1];
@@ -599,13 +602,13 @@ __global__ void __launch_bounds__(NTHREADS) batched_step_kernel(const ShotDesc* 
     a.trace_row = nullptr;
   }
   a.samp_out = (n >= 1 && sd->nrec > 0) ? sd->traces + (int64_t)(n - 1) * sd->nrec : nullptr;
-  if (e.tile < 0) {
-    const int r = (-1 - e.tile) * NTHREADS + threadIdx.x;
+  if (e.xy < 0) {
+    const int r = (-1 - e.xy) * NTHREADS + threadIdx.x;
     if (a.samp_out != nullptr && r < a.nsamp)
       a.samp_out[r] = sample_point<ST_F32>(a.cur, 1.f, a.samp_idx, a.samp_w, r);
     return;
   }
-  if (n < nt) step_tile<R, false, ST_F32, false, false>(a, e.tile, 1.f, 1.f, 1.f, 1.f);
+  if (n < nt) step_tile<R, false, ST_F32, false, false>(a, e.xy, e.z0, e.z1, 1.f, 1.f, 1.f, 1.f);
 }
 
 // Copy each listed shot's counter of parity 0 into out (host read-back after a replay).

@@ -5,9 +5,10 @@
 // on tile and chunk edges -- the tables are checked against a brute-force
 // reference written here from the definition: every point contributes its
 // trilinear corners (weights (1-t) or t per axis, corners of weight 0 dropped);
-// each distinct grid point becomes one entry of the tile that holds it, entries
-// ordered by (tile, plane, index in the tile), with the contributing (point,
-// weight) terms in point order. Built and run by tests/test_tables_host.py; exits
+// each distinct grid point becomes one entry of the column (xy tile, plane) that
+// holds it, columns numbered (ty * ntile_x + tx) * nz + z, entries ordered by
+// (column, index in the tile), with the contributing (point, weight) terms in
+// point order; the tables do not depend on the z-chunking. Built and run by tests/test_tables_host.py; exits
 // non-zero on failure.
 #include <cmath>
 #include <cstdio>
@@ -60,7 +61,7 @@ static void reference(const wave_grid& g, const Geom& G, const Tiling& T,
       (*sidx)[8 * p + k] = (int)((int64_t)z * G.plane + (int64_t)j * G.pitch + i);
       (*sw)[8 * p + k] = (float)w;
       ++k;
-      const int tile = ((z / T.zchunk) * T.ntile_y + j / TY) * T.ntile_x + i / TX;
+      const int tile = ((j / TY) * T.ntile_x + i / TX) * G.nz + z;
       (*ent)[RefKey{tile, z, (j % TY) * TX + (i % TX)}].push_back(RefTerm{p, (float)w});
     }
   }
@@ -92,7 +93,8 @@ static void check_tables(const wave_grid& g, int zchunk, const std::vector<doubl
   const InjEntry* ent = B.at<InjEntry>(P.ent);
   const int* cidx = B.at<int>(P.csr_idx);
   const float* cw = B.at<float>(P.csr_w);
-  CHECK(tb[0] == 0 && tb[T.nblocks] == (int)ref.size());
+  const int ncol = T.ntile_x * T.ntile_y * G.nz;
+  CHECK(tb[0] == 0 && tb[ncol] == (int)ref.size());
   int e = 0, c = 0;
   for (const auto& kv : ref) {
     const int tile = std::get<0>(kv.first);
@@ -115,14 +117,14 @@ static void check_tables(const wave_grid& g, int zchunk, const std::vector<doubl
     CHECK(en.grp_end == q);
     ++e;
   }
-  for (int t = 0; t < T.nblocks; ++t) CHECK(tb[t] <= tb[t + 1]);
+  for (int t = 0; t < ncol; ++t) CHECK(tb[t] <= tb[t + 1]);
   // uploaded ranges: every written array, within the table region
   size_t covered = 0;
   for (const auto& r : B.used) {
     CHECK(r.first + r.second <= size);
     covered += r.second;
   }
-  const size_t want = ((size_t)T.nblocks + 1) * sizeof(int) + (size_t)e * sizeof(InjEntry) +
+  const size_t want = ((size_t)ncol + 1) * sizeof(int) + (size_t)e * sizeof(InjEntry) +
                       (size_t)c * (sizeof(int) + sizeof(float)) +
                       (size_t)8 * np * (sizeof(int) + sizeof(float));
   CHECK(covered == want);
