@@ -597,8 +597,12 @@ def main():
                    "nrec": args.n, "storage": "f32"},
         "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
                      "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
-                     "traffic": measured_traffic(),
-                     "kernel": "step_kernel<%d,false>" % (args.so // 2),
+                     # the committed counters cover the 256^3 SO8 one-step kernel only
+                     "traffic": measured_traffic() if (args.n, args.so, args.kernel) in
+                     ((256, 8, "default"), (256, 8, "one_step")) else None,
+                     "kernel": ("fused2_kernel<%d> (16 B/pt one-step equivalent)"
+                                if args.kernel == "two_step" else "step_kernel<%d,false>")
+                     % (args.so // 2),
                      "alg_bytes_per_launch": ALG_BYTES_PER_PT * npts,
                      "avg_launch_us": round(launch_s * 1e6, 3),
                      "kernel_source_hash": kernel_hash()},
