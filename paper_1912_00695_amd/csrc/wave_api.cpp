@@ -351,11 +351,13 @@ constexpr int64_t kFusedMinPoints[5] = {0, 30000000, 60000000, 80000000, 1200000
 constexpr int kFusedZChunk = 64;
 int fused_zchunk(const wave_grid* g) {
   const int r = g->so / 2;
-  if (r == 4) {  // 128-plane chunks where they still give 512 workgroups or more
-    const int64_t tiles = (int64_t)((g->nx + TX - 1) / TX) *
-                          ((g->ny + f2_tiles_y(r) * TY - 1) / (f2_tiles_y(r) * TY)) *
-                          ((g->nz + 127) / 128);
-    if (tiles >= 512) return 128;
+  if (r == 4) {  // one 768-thread workgroup per CU: 128-plane chunks where they still
+                 // give 512 workgroups, else 64 or 32 planes for at least 256
+    const int64_t cols = (int64_t)((g->nx + TX - 1) / TX) *
+                         ((g->ny + f2_tiles_y(r) * TY - 1) / (f2_tiles_y(r) * TY));
+    if (cols * ((g->nz + 127) / 128) >= 512) return 128;
+    if (cols * ((g->nz + 63) / 64) >= 256) return 64;
+    return 32;
   }
   return kFusedZChunk;
 }
