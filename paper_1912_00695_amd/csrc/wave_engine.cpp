@@ -12,13 +12,16 @@
 //     the GPU);
 //   * resident shots advance in groups (one space order, per-step arrays that fit
 //     the Infinity Cache together): a captured graph of kReplaySteps launches of
-//     the batched step kernel per group, group after group, is replayed; per-shot
-//     step counters live in device memory, so one graph serves any mix of shots at
-//     any step, and is re-captured only when the set of resident shots changes;
-//   * the graph is launched several times back to back (about kSyncWork of
-//     estimated GPU time) before the worker reads the counters back, retires
-//     finished shots (traces copied to the caller's host buffer, pool space
-//     freed, latency recorded) and admits more.
+//     the batched step kernel per group, group after group, is replayed; each
+//     group's launch table lists (shot, xy tile, planes) per workgroup, with the
+//     group's own z-chunk length; per-shot step counters live in device memory, so
+//     one graph serves any mix of shots at any step, and is re-captured only when
+//     the set of resident shots changes;
+//   * the graph is launched several times back to back (up to the first shot's
+//     finish, bounded by kSyncWork of estimated GPU time while requests wait)
+//     before the worker reads the counters back, completes finished shots (traces
+//     copied to the caller's host buffer, latency recorded; their pool space is
+//     freed at the next rebuild) and admits more.
 // Every shot's arithmetic is the single-shot kernel's (shared tile function), so
 // a result does not depend on the batch it ran in.
 #include <hip/hip_runtime.h>
