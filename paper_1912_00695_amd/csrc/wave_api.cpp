@@ -643,7 +643,9 @@ StepArgs base_args(const Ctx& C) {
   a.ntile_y = C.T.ntile_y;
   a.nchunk = C.T.nchunk;
   a.zchunk = C.T.zchunk;
-  a.nstencil_blocks = C.T.nblocks;
+  // the one-step kernel's workgroups tile step_tiles_y(r) one-step tiles along y
+  const int ky = step_tiles_y(C.g->so / 2);
+  a.nstencil_blocks = C.T.ntile_x * ((C.T.ntile_y + ky - 1) / ky) * C.T.nchunk;
   a.xcd_remap = (C.g->path & WAVE_PATH_LINEAR) == 0;
   for (int q = 0; q <= MAXR; ++q) {
     a.wx[q] = (float)C.wx[q];

@@ -68,18 +68,20 @@ constexpr bool halo_ring(int r) { return ((WAVE_HRING_MASK) >> r) & 1; }
 // ntile_x + tx) over planes [z0, z1). Shared by the single-shot kernel and the
 // batched serving kernel, so a shot's values do not depend on what else is in the
 // launch or on how its planes are chunked.
-template <int R, bool GRAD, int ST, bool DIFF, bool NT, bool BASIC = false>
+template <int R, bool GRAD, int ST, bool DIFF, bool NT, bool BASIC = false, int K = 1>
 __device__ __forceinline__ void step_tile(const StepArgs& a, const int xy, const int z0,
                                           const int z1, const float dec_c, const float dec_p,
                                           const float enc_u, const float enc_d) {
+  constexpr int TYK = K * TY;        // rows of the tile (K one-step tiles)
+  constexpr int NTH = K * NTHREADS;  // threads of the workgroup
   constexpr int XH = R <= 4 ? 4 : (R <= 8 ? 8 : 12);  // x-halo width (multiple of 4)
   constexpr int XH4 = XH / 4;
   constexpr int LROW4 = NTX + 2 * XH4;  // float4 per LDS row
-  constexpr int LROWS = TY + 2 * R;
-  constexpr int NH = 2 * R * NTX + 2 * TY * XH4;  // halo float4 per plane
-  constexpr int NHP = (NH + NTHREADS - 1) / NTHREADS;
+  constexpr int LROWS = TYK + 2 * R;
+  constexpr int NH = 2 * R * NTX + 2 * TYK * XH4;  // halo float4 per plane
+  constexpr int NHP = (NH + NTH - 1) / NTH;
   __shared__ float4 lds[2][LROWS * LROW4];
-  __shared__ float4 inj[TY * NTX];
+  __shared__ float4 inj[TYK * NTX];
   __shared__ float bzs[MAXZCHUNK];  // z sponge factors of the chunk (read from LDS in the
                                     // sweep, so no vector load there waits on the prefetch)
   // Halo ring: the xy-halo of plane p is read by this workgroup when p is staged,
@@ -99,8 +101,8 @@ __device__ __forceinline__ void step_tile(const StepArgs& a, const int xy, const
   const auto hslot = [](const int p) { return p % (R + 1); };  // p >= 0
 
   const int tx_t = xy % a.ntile_x;
-  const int ty_t = xy / a.ntile_x;
-  const int xt = tx_t * TX, yt = ty_t * TY;
+  const int ty_t = xy / a.ntile_x;  // in tiles of TYK rows
+  const int xt = tx_t * TX, yt = ty_t * TYK;
   const int nx = a.g.nx, ny = a.g.ny, nz = a.g.nz;
   const int64_t plane = a.g.plane;
   const int tid = threadIdx.x;
@@ -116,7 +118,7 @@ __device__ __forceinline__ void step_tile(const StepArgs& a, const int xy, const
   bool hok[NHP];
 #pragma unroll
   for (int k = 0; k < NHP; ++k) {
-    const int i = tid + k * NTHREADS;
+    const int i = tid + k * NTH;
     int gy = 0, gx = 0, row = 0, c4 = 0;
     bool in = i < NH;
     if (i < R * NTX) {
@@ -124,14 +126,14 @@ __device__ __forceinline__ void step_tile(const StepArgs& a, const int xy, const
       gy = yt - R + row; gx = xt + 4 * (i % NTX);
     } else if (i < 2 * R * NTX) {
       const int j = i - R * NTX;
-      row = R + TY + j / NTX; c4 = XH4 + j % NTX;
-      gy = yt + TY + j / NTX; gx = xt + 4 * (j % NTX);
-    } else if (i < 2 * R * NTX + TY * XH4) {
+      row = R + TYK + j / NTX; c4 = XH4 + j % NTX;
+      gy = yt + TYK + j / NTX; gx = xt + 4 * (j % NTX);
+    } else if (i < 2 * R * NTX + TYK * XH4) {
       const int j = i - 2 * R * NTX;
       row = R + j / XH4; c4 = j % XH4;
       gy = yt + j / XH4; gx = xt - XH + 4 * (j % XH4);
     } else {
-      const int j = i - 2 * R * NTX - TY * XH4;
+      const int j = i - 2 * R * NTX - TYK * XH4;
       row = R + j / XH4; c4 = XH4 + NTX + j % XH4;
       gy = yt + j / XH4; gx = xt + TX + 4 * (j % XH4);
     }
@@ -217,25 +219,38 @@ __device__ __forceinline__ void step_tile(const StepArgs& a, const int xy, const
       for (int j = 1; j <= R; ++j)
 #pragma unroll
         for (int k = 0; k < NHP; ++k)
-          if (hlds[k] >= 0) hbuf[hslot(z0 + j)][tid + k * NTHREADS] = hq[j - 1][k];
+          if (hlds[k] >= 0) hbuf[hslot(z0 + j)][tid + k * NTH] = hq[j - 1][k];
     }
   }
   inj[tid] = zero4;
   if (tid < z1 - z0) bzs[tid] = gmem(a.bz)[z0 + tid];
   __syncthreads();
 
-  // Injection entries of this tile (sorted by plane); ez is the plane of the next
-  // group, kept in a register so the per-plane test needs no load.
-  int e = 0, e_end = 0, ez = INT_MAX, eg = 0;  // eg: end of the group at plane ez
+  // Injection entries of the tile's K one-step tiles on planes [z0, z1) (sorted by
+  // plane); ezk[k] is the plane of sub-tile k's next group and ez the nearest of
+  // them, kept in registers so the per-plane test needs no load.
+  int e[K], e_end[K], ezk[K], eg[K];  // eg[k]: end of sub-tile k's group at ezk[k]
   const auto* ent = gmem(a.ent);
-  if (a.tile_beg != nullptr) {
-    e = gmem(a.tile_beg)[xy * nz + z0];
-    e_end = gmem(a.tile_beg)[xy * nz + z1];
-    if (e < e_end) {
-      ez = ent[e].z;
-      eg = ent[e].grp_end;
+#pragma unroll
+  for (int k = 0; k < K; ++k) {
+    e[k] = 0;
+    e_end[k] = 0;
+    ezk[k] = INT_MAX;
+    eg[k] = 0;
+    const int ty1 = K * ty_t + k;  // one-step tile row
+    if (a.tile_beg != nullptr && (K == 1 || ty1 < a.ntile_y)) {
+      const int xy1 = ty1 * a.ntile_x + tx_t;
+      e[k] = gmem(a.tile_beg)[xy1 * nz + z0];
+      e_end[k] = gmem(a.tile_beg)[xy1 * nz + z1];
+      if (e[k] < e_end[k]) {
+        ezk[k] = ent[e[k]].z;
+        eg[k] = ent[e[k]].grp_end;
+      }
     }
   }
+  int ez = ezk[0];
+#pragma unroll
+  for (int k = 1; k < K; ++k) ez = min(ez, ezk[k]);
 
   // Loads that plane zn needs before its own step, kept raw until used: the
   // queue head (plane zn+R), the xy-halo of plane zn (with the halo ring: of plane
@@ -311,28 +326,40 @@ __device__ __forceinline__ void step_tile(const StepArgs& a, const int xy, const
 
     // Fused injection at this plane (uniform branch).
     if (z == ez) {
-      for (int i = e + tid; i < eg; i += NTHREADS) {
-        const InjEntry en = ent[i];
-        const auto* row = gmem(a.trace_row);
-        float s = 0.f;
-        if (en.tidx >= 0) {  // single term, carried in the entry
-          s = fmaf(en.w, row[en.tidx], 0.f);
-        } else {
-          for (int c = en.csr_beg; c < en.csr_end; ++c)
-            s = fmaf(gmem(a.csr_w)[c], row[gmem(a.csr_idx)[c]], s);
+#pragma unroll
+      for (int k = 0; k < K; ++k) {
+        if (ezk[k] != z) continue;
+        // sub-tile k holds tile rows k*TY .. k*TY+TY-1: local indices offset by k*TY*TX
+        for (int i = e[k] + tid; i < eg[k]; i += NTH) {
+          const InjEntry en = ent[i];
+          const auto* row = gmem(a.trace_row);
+          float s = 0.f;
+          if (en.tidx >= 0) {  // single term, carried in the entry
+            s = fmaf(en.w, row[en.tidx], 0.f);
+          } else {
+            for (int c = en.csr_beg; c < en.csr_end; ++c)
+              s = fmaf(gmem(a.csr_w)[c], row[gmem(a.csr_idx)[c]], s);
+          }
+          reinterpret_cast<float*>(inj)[k * TY * TX + en.local] = s;
         }
-        reinterpret_cast<float*>(inj)[en.local] = s;
       }
       __syncthreads();
       const float4 iv = inj[tid];
       lap[0] += iv.x; lap[1] += iv.y; lap[2] += iv.z; lap[3] += iv.w;
       inj[tid] = zero4;
-      e = eg;
-      ez = INT_MAX;
-      if (e < e_end) {
-        ez = ent[e].z;
-        eg = ent[e].grp_end;
+#pragma unroll
+      for (int k = 0; k < K; ++k) {
+        if (ezk[k] != z) continue;
+        e[k] = eg[k];
+        ezk[k] = INT_MAX;
+        if (e[k] < e_end[k]) {
+          ezk[k] = ent[e[k]].z;
+          eg[k] = ent[e[k]].grp_end;
+        }
       }
+      ez = ezk[0];
+#pragma unroll
+      for (int k = 1; k < K; ++k) ez = min(ez, ezk[k]);
     }
 
     // Damped leapfrog update in increment form:
@@ -449,13 +476,13 @@ __device__ __forceinline__ void step_tile(const StepArgs& a, const int xy, const
       for (int k = 0; k < NHP; ++k)
         if (hlds[k] >= 0)
           lds[buf ^ 1][hlds[k]] =
-              wcur(HRG ? hbuf[hslot(z + 1)][tid + k * NTHREADS] : n1.h[k]);
+              wcur(HRG ? hbuf[hslot(z + 1)][tid + k * NTH] : n1.h[k]);
     }
     if constexpr (HRG) {
       if (z + 1 + R < z1) {
 #pragma unroll
         for (int k = 0; k < NHP; ++k)
-          if (hlds[k] >= 0) hbuf[hslot(z + 1 + R)][tid + k * NTHREADS] = n1.h[k];
+          if (hlds[k] >= 0) hbuf[hslot(z + 1 + R)][tid + k * NTH] = n1.h[k];
       }
     }
     __syncthreads();
@@ -495,7 +522,7 @@ __device__ __forceinline__ void step_tile(const StepArgs& a, const int xy, const
   if constexpr (ST != ST_F32) {
     // Maxima of the level just written, for the next step's scale choice: reduced
     // over the workgroup, then one atomic per workgroup into its slot.
-    __shared__ float wm[2][NTHREADS / 64];
+    __shared__ float wm[2][NTH / 64];
     mx_u = wave_max(mx_u);
     if (DIFF) mx_d = wave_max(mx_d);
     if ((tid & 63) == 0) {
@@ -506,7 +533,7 @@ __device__ __forceinline__ void step_tile(const StepArgs& a, const int xy, const
     if (tid == 0) {
       float mu = wm[0][0], md = wm[1][0];
 #pragma unroll
-      for (int w = 1; w < NTHREADS / 64; ++w) {
+      for (int w = 1; w < NTH / 64; ++w) {
         mu = fmaxf(mu, wm[0][w]);
         md = fmaxf(md, wm[1][w]);
       }
@@ -526,7 +553,9 @@ __device__ __forceinline__ float level_max(const unsigned* arr, int i) {
 }
 
 template <int R, bool GRAD, int ST, bool DIFF, bool NT, bool BASIC = false>
-__global__ void __launch_bounds__(NTHREADS) step_kernel(const StepArgs a) {
+__global__ void __launch_bounds__(step_tiles_y(R) * NTHREADS) step_kernel(const StepArgs a) {
+  constexpr int K = step_tiles_y(R);
+  constexpr int NTH = K * NTHREADS;
   // Per-level scales of reduced-precision storage: decode cur and prev, choose
   // the encode scales of the level written here from the previous maxima.
   float dec_c = 1.f, dec_p = 1.f, enc_u = 1.f, enc_d = 1.f;
@@ -554,17 +583,18 @@ __global__ void __launch_bounds__(NTHREADS) step_kernel(const StepArgs a) {
   }
   const int bid = blockIdx.x;
   if (bid >= a.nstencil_blocks) {
-    const int r = (bid - a.nstencil_blocks) * NTHREADS + threadIdx.x;
+    const int r = (bid - a.nstencil_blocks) * NTH + threadIdx.x;
     if (a.samp_out != nullptr && r < a.nsamp)
       a.samp_out[r] = sample_point<ST>(a.cur, dec_c, a.samp_idx, a.samp_w, r);
     return;
   }
-  // logical tile t = (chunk * ntile_y + ty) * ntile_x + tx
+  // logical tile t = (chunk * ntile_yK + ty) * ntile_x + tx, in tiles of K one-step
+  // tiles along y
   const int t = a.xcd_remap ? remap_tile(bid, a.nstencil_blocks) : bid;
-  const int bxy = a.ntile_x * a.ntile_y;
+  const int bxy = a.ntile_x * ((a.ntile_y + K - 1) / K);
   const int z0 = (t / bxy) * a.zchunk;
-  step_tile<R, GRAD, ST, DIFF, NT, BASIC>(a, t % bxy, z0, min(z0 + a.zchunk, a.g.nz), dec_c, dec_p,
-                                          enc_u, enc_d);
+  step_tile<R, GRAD, ST, DIFF, NT, BASIC, K>(a, t % bxy, z0, min(z0 + a.zchunk, a.g.nz), dec_c,
+                                             dec_p, enc_u, enc_d);
 }
 
 // Serving: one launch advances every active shot of one space order by a step.
@@ -784,8 +814,9 @@ int elementwise_blocks(int64_t n) {
 
 template <int R, bool GRAD, int ST, bool DIFF, bool NT>
 hipError_t launch_r(const StepArgs& a, hipStream_t s) {
-  const int nsamp_blocks = a.samp_out != nullptr ? (a.nsamp + NTHREADS - 1) / NTHREADS : 0;
-  const dim3 grid(a.nstencil_blocks + nsamp_blocks), block(NTHREADS);
+  constexpr int nth = step_tiles_y(R) * NTHREADS;
+  const int nsamp_blocks = a.samp_out != nullptr ? (a.nsamp + nth - 1) / nth : 0;
+  const dim3 grid(a.nstencil_blocks + nsamp_blocks), block(nth);
   hipLaunchKernelGGL((step_kernel<R, GRAD, ST, DIFF, NT>), grid, block, 0, s, a);
   return hipGetLastError();
 }
@@ -813,8 +844,10 @@ hipError_t launch_variant(const StepArgs& a, bool grad, int st, bool diff, bool 
 }  // namespace
 
 hipError_t launch_step_basic(const StepArgs& a, int r, hipStream_t s) {
-  const int nsb = a.samp_out != nullptr ? (a.nsamp + NTHREADS - 1) / NTHREADS : 0;
-  const dim3 grid(a.nstencil_blocks + nsb), block(NTHREADS);
+  if (r < 1 || r > MAXR) return hipErrorInvalidValue;
+  const int nth = step_tiles_y(r) * NTHREADS;
+  const int nsb = a.samp_out != nullptr ? (a.nsamp + nth - 1) / nth : 0;
+  const dim3 grid(a.nstencil_blocks + nsb), block(nth);
   switch (r) {
     case 4: hipLaunchKernelGGL((step_kernel<4, false, ST_F32, false, false, true>), grid, block, 0, s, a); break;
     case 6: hipLaunchKernelGGL((step_kernel<6, false, ST_F32, false, false, true>), grid, block, 0, s, a); break;

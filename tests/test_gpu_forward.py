@@ -282,3 +282,39 @@ def test_concurrent_calls_on_two_streams():
     for k, o in outs:
         assert np.array_equal(o["rec"].cpu().numpy(), alone[k]["rec"])
         assert np.array_equal(o["u_final"].cpu().numpy(), alone[k]["u_final"])
+
+
+@pytest.mark.parametrize("so", [8, 16, 20])
+def test_tall_tiles_sources_on_tile_edges(so):
+    """Sources and receivers on and next to the edges of one-step tiles (y = 15 / 16,
+    47 / 48) and of the two-tile workgroup tiles that SO16 and SO20 use (y = 31 / 32,
+    63 / 64), on x-tile edges (63 / 64) and z-chunk edges (8-plane chunks), on a grid whose
+    last workgroup tile holds a single one-step tile (ny = 80): against the oracle, and
+    the same request through the serving engine (one-step tiles, the engine's own
+    chunking) bitwise against wave_forward."""
+    import torch
+    from helpers import Case
+    from paper_1912_00695_amd import inputs, serving, wave
+    n, h = (130, 80, 40), (10.0, 10.0, 10.0)
+    vel = inputs.smooth_random_range(n, 1500.0, 2500.0, 8.0, seed=70 + so)
+    case = Case(n, h, so, 40, vel, 2500.0, nbl=(6,) * 6)
+    pts = [(63, 15, 7), (64, 16, 8), (63.5, 31.5, 15.5), (10, 32, 16), (100, 47, 23),
+           (64.25, 48, 24), (30, 63, 31.75), (31, 64, 20), (120.5, 79, 12), (5, 0.5, 33)]
+    case.src = np.array([[p[0] * h[0], p[1] * h[1], p[2] * h[2]] for p in pts])
+    case.wavelet = np.random.default_rng(71).standard_normal((case.nt, len(pts))).astype(np.float32)
+    case.rec = np.concatenate([case.src, inputs.random_points(n, h, 40, 72)])
+    print("tall tiles: SO", so, "edge sources", flush=True)
+    g = _run(case, zchunk=8)
+    rec, uf, _ = case.oracle_forward()
+    e_u, e_r = rel_l2(g["u_final"], uf), rel_l2(g["rec"], rec)
+    print("  field %.3e traces %.3e" % (e_u, e_r), flush=True)
+    assert e_u <= TOL and e_r <= TOL
+    dev = torch.device("cuda:0")
+    grid = case.wgrid()
+    f = wave.forward(grid, torch.from_numpy(case.vel).to(dev),
+                     torch.from_numpy(case.wavelet).to(dev), case.src, case.rec)["rec"].cpu().numpy()
+    with serving.Engine(4 << 30, 4) as eng:
+        _, o = eng.submit(grid, case.vel, case.wavelet, case.src, case.rec)
+        eng.drain(120)
+    print("  engine equals wave_forward:", np.array_equal(o, f), flush=True)
+    assert np.array_equal(o, f)
