@@ -124,7 +124,7 @@ typedef struct {
                           bits: WAVE_EINVAL                                          */
   int32_t zchunk;      /* planes per z-chunk of the stencil sweep, 1..256 (0 = chosen
                           by the library: about 512 workgroups; 64 planes for the
-                          two-step kernel); results do not depend on it              */
+                          two-step kernel, 32-128 at SO8); results do not depend on it */
 } wave_grid;
 
 /* Largest stable dt of the leapfrog scheme (von Neumann):
@@ -296,7 +296,9 @@ typedef struct {
  * groups of one space order whose per-step arrays fit the Infinity Cache together
  * (224 MB unless wave_engine_set_group_bytes says otherwise), several steps of a
  * group back to back; a shot's results do not depend on the grouping or on the
- * other shots. A request's zchunk (0: 32 planes) sets its tiling in the engine. */
+ * other shots. A request's zchunk fixes its z-chunk length in the engine; 0 lets the
+ * engine choose per group (the longest of 32, 24, ..., 1 planes that gives the
+ * group 512 workgroups). */
 int wave_engine_create(size_t hbm_budget_bytes, int max_slots, void** engine);
 /* Per-step bytes (two FP32 levels and v^2 dt^2) of the shots stepped together in
  * one group; 0 restores the default. Applies from the next change of the set of
