@@ -100,6 +100,11 @@ extern "C" {
  * then on. The replay runs the same kernels with the same arguments. */
 #define WAVE_PATH_GRAPH 32    /* capture and replay from the first call               */
 #define WAVE_PATH_DIRECT 64   /* always launch directly (no graph)                     */
+/* Workgroup tile of the one-step kernel: 64 x 16 points, or 64 x 32 at SO 8, 16 and 20
+ * (the orders that have it). By default the taller tile is taken at those orders when
+ * the grid still gives each of the GPU's 256 CUs a workgroup. */
+#define WAVE_PATH_TILE16 128  /* 64 x 16 tiles                                         */
+#define WAVE_PATH_TILE32 256  /* 64 x 32 tiles at SO 8, 16 and 20                      */
 
 /* Workspace modes for wave_workspace_bytes(). */
 #define WAVE_MODE_FORWARD 0
@@ -120,8 +125,8 @@ typedef struct {
   int32_t storage;     /* WAVE_STORE_F32 | WAVE_STORE_F16 | WAVE_STORE_BF16, the last two
                           optionally | WAVE_STORE_DIFF                               */
   int32_t path;        /* WAVE_PATH_* flags (0 = chosen by the library); ONE_STEP with
-                          TWO_STEP, STREAM with CACHED, GRAPH with DIRECT, or unknown
-                          bits: WAVE_EINVAL                                          */
+                          TWO_STEP, STREAM with CACHED, GRAPH with DIRECT, TILE16 with
+                          TILE32, or unknown bits: WAVE_EINVAL                       */
   int32_t zchunk;      /* planes per z-chunk of the stencil sweep, 1..256 (0 = chosen
                           by the library: about 512 workgroups; 64 planes for the
                           two-step kernel, 32-128 at SO8); results do not depend on it */

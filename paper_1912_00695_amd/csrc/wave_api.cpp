@@ -53,8 +53,10 @@ bool grid_ok(const wave_grid* g) {
   if (st != WAVE_STORE_F32 && st != WAVE_STORE_F16 && st != WAVE_STORE_BF16) return false;
   if (st == WAVE_STORE_F32 && (g->storage & WAVE_STORE_DIFF)) return false;
   if (g->path & ~(WAVE_PATH_ONE_STEP | WAVE_PATH_TWO_STEP | WAVE_PATH_STREAM |
-                  WAVE_PATH_CACHED | WAVE_PATH_LINEAR | WAVE_PATH_GRAPH | WAVE_PATH_DIRECT))
+                  WAVE_PATH_CACHED | WAVE_PATH_LINEAR | WAVE_PATH_GRAPH | WAVE_PATH_DIRECT |
+                  WAVE_PATH_TILE16 | WAVE_PATH_TILE32))
     return false;
+  if ((g->path & WAVE_PATH_TILE16) && (g->path & WAVE_PATH_TILE32)) return false;
   if ((g->path & WAVE_PATH_GRAPH) && (g->path & WAVE_PATH_DIRECT)) return false;
   if ((g->path & WAVE_PATH_ONE_STEP) && (g->path & WAVE_PATH_TWO_STEP)) return false;
   if ((g->path & WAVE_PATH_STREAM) && (g->path & WAVE_PATH_CACHED)) return false;
@@ -93,7 +95,7 @@ Geom make_geom(const wave_grid* g) {
 // would need more than 1024 workgroups at 32 planes: 546 Gpt/s at 512^3 SO8 against
 // 498 with one long chunk per workgroup. A positive zchunk fixes the chunk length
 // (the grid's zchunk, or the caller's policy).
-Tiling make_tiling(const Geom& G, int zchunk, bool short_chunks) {
+Tiling make_tiling(const Geom& G, int r, int path, int zchunk, bool short_chunks) {
   Tiling T;
   T.ntile_x = (G.nx + TX - 1) / TX;
   T.ntile_y = (G.ny + TY - 1) / TY;
@@ -114,6 +116,18 @@ Tiling make_tiling(const Geom& G, int zchunk, bool short_chunks) {
   T.zchunk = zc;
   T.nchunk = (G.nz + zc - 1) / zc;
   T.nblocks = bxy * T.nchunk;
+  // Workgroup height of the one-step kernel: two one-step tiles along y where the
+  // radius has that form and the taller workgroups fill the 256 CUs evenly (a
+  // multiple of 256). Measured at SO8 with the chunks above: 256^3 +6.6 % and 512^3
+  // +2.2 % (256 workgroups each); 320^3 -6 %, 384^3 -6 %, 448^3 -4 % (250, 216 and 196
+  // workgroups: idle CUs). Uneven counts are worse still: a CU given two of them runs
+  // out of VALU issue (the kernel keeps about 45 % of it busy at SO8): 288 workgroups
+  // at 384^3 (96-plane chunks) -23 %.
+  T.tiles_y = 1;
+  if (tall_tiles_ok(r) && !(path & WAVE_PATH_TILE16)) {
+    const int64_t tall = (int64_t)T.ntile_x * ((T.ntile_y + 1) / 2) * T.nchunk;
+    if ((path & WAVE_PATH_TILE32) || (tall >= kCUs && tall % kCUs == 0)) T.tiles_y = 2;
+  }
   return T;
 }
 
@@ -540,7 +554,7 @@ int init_ctx(Ctx& C, const wave_grid* g, int nsrc, int nrec, int mode, int ckpt_
              size_t ws_bytes, void* stream, int zchunk, bool fused_levels) {
   C.g = g;
   C.G = make_geom(g);
-  C.T = make_tiling(C.G, zchunk > 0 ? zchunk : g->zchunk,
+  C.T = make_tiling(C.G, g->so / 2, g->path, zchunk > 0 ? zchunk : g->zchunk,
                     store_kind(g) != WAVE_STORE_F32 && !store_diff(g));
   C.L = make_layout(g, nsrc, nrec, mode, ckpt_every, fused_levels);
   if (ws == nullptr || (reinterpret_cast<uintptr_t>(ws) % kAlign) != 0) return WAVE_EINVAL;
@@ -643,9 +657,9 @@ StepArgs base_args(const Ctx& C) {
   a.ntile_y = C.T.ntile_y;
   a.nchunk = C.T.nchunk;
   a.zchunk = C.T.zchunk;
-  // the one-step kernel's workgroups tile step_tiles_y(r) one-step tiles along y
-  const int ky = step_tiles_y(C.g->so / 2);
-  a.nstencil_blocks = C.T.ntile_x * ((C.T.ntile_y + ky - 1) / ky) * C.T.nchunk;
+  // the one-step kernel's workgroups tile T.tiles_y one-step tiles along y
+  a.tiles_y = C.T.tiles_y;
+  a.nstencil_blocks = C.T.ntile_x * ((C.T.ntile_y + a.tiles_y - 1) / a.tiles_y) * C.T.nchunk;
   a.xcd_remap = (C.g->path & WAVE_PATH_LINEAR) == 0;
   for (int q = 0; q <= MAXR; ++q) {
     a.wx[q] = (float)C.wx[q];

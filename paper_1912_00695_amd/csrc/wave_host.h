@@ -16,8 +16,11 @@ namespace wave {
 constexpr size_t kAlign = 256;
 constexpr int kDefaultCkpt = 50;
 
+constexpr int kCUs = 256;  // compute units of an MI355X
+
 struct Tiling {
-  int ntile_x, ntile_y, nchunk, zchunk, nblocks;
+  int ntile_x, ntile_y, nchunk, zchunk, nblocks;  // in one-step (TX x TY) tiles
+  int tiles_y;  // one-step tiles per workgroup of the one-step kernel along y
 };
 
 struct PointTables {  // offsets into the workspace
@@ -95,8 +98,9 @@ bool grid_ok(const wave_grid* g);
 int validate(const wave_grid* g);  // grid_ok + stability limit
 bool points_ok(const wave_grid* g, const double* xyz, int np);
 Geom make_geom(const wave_grid* g);
-// zchunk > 0 fixes the z-chunk length; 0 applies the single-solve policy
-Tiling make_tiling(const Geom& G, int zchunk = 0, bool short_chunks = false);
+// zchunk > 0 fixes the z-chunk length; 0 applies the single-solve policy. r and path
+// (WAVE_PATH_* flags) choose the one-step kernel's workgroup height.
+Tiling make_tiling(const Geom& G, int r, int path, int zchunk, bool short_chunks);
 // fused_levels: an FP32 forward layout at radius <= 4 also holds the two-step
 // kernel's two extra levels and extended-tile tables (false: one-step only)
 Layout make_layout(const wave_grid* g, int nsrc, int nrec, int mode, int ckpt_every,

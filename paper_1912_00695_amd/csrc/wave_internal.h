@@ -17,17 +17,18 @@ constexpr int NTX = TX / VX;     // threads along x
 constexpr int NTHREADS = NTX * TY;
 constexpr int MAXR = 12;         // SO <= 24
 constexpr int MAXZCHUNK = 256;   // planes per z-chunk at most (<= NTHREADS)
-// One-step tiles stacked along y in one workgroup's tile of the one-step kernel,
-// per radius r: 1 (TX x TY points, NTHREADS threads), or 2 (TX x 2TY points, twice
-// the threads: half the y-halo per point) where bit r of WAVE_TALL_MASK is set. The
-// injection tables stay in TY-row tiles; a taller tile reads them per sub-tile.
-// Measured at 256^3 (one 512-thread workgroup per CU instead of two of 256): SO16
-// +2.5 %, SO20 +2.2 %; but SO18 -6.7 %, SO22 -4.8 %, SO24 -3.3 %; SO8 and SO12 keep
-// one-step tiles.
+// One-step tiles stacked along y in one workgroup's tile of the one-step kernel:
+// 1 (TX x TY points, NTHREADS threads) or 2 (TX x 2TY points, twice the threads:
+// half the y-halo per point). The taller tile exists for the radii whose bit is set
+// in WAVE_TALL_MASK; the host picks it per call (StepArgs::tiles_y) where the grid
+// still gives every CU a workgroup. The injection tables stay in TY-row tiles; a
+// taller tile reads them per sub-tile. Measured at 256^3 (one 512-thread workgroup
+// per CU instead of two of 256): SO8 +5.5 %, SO16 +2.5 %, SO20 +2.2 %; SO18 -6.7 %,
+// SO22 -4.8 %, SO24 -3.3 %.
 #ifndef WAVE_TALL_MASK
-#define WAVE_TALL_MASK 0x500  // radius 8 and 10
+#define WAVE_TALL_MASK 0x510  // radius 4, 8 and 10
 #endif
-constexpr int step_tiles_y(int r) { return (((WAVE_TALL_MASK) >> r) & 1) ? 2 : 1; }
+constexpr bool tall_tiles_ok(int r) { return (((WAVE_TALL_MASK) >> r) & 1) != 0; }
 constexpr int SAMPLE_THREADS = 256;
 
 // Pitched field geometry: rows padded to a multiple of 32 floats (128 bytes);
@@ -89,6 +90,7 @@ struct StepArgs {
   // tiling
   int ntile_x, ntile_y, nchunk, zchunk;
   int nstencil_blocks;
+  int tiles_y;        // one-step tiles per workgroup along y (1, or 2 where tall_tiles_ok)
   int xcd_remap;      // 1: contiguous tile ranges per XCD
   // weights pre-scaled by h_a^-2; wc = -2 sum_{q>=2} (wx+wy+wz) (the q = 1 pairs are
   // taken about the centre)

@@ -552,9 +552,9 @@ __device__ __forceinline__ float level_max(const unsigned* arr, int i) {
   return __uint_as_float(m);
 }
 
-template <int R, bool GRAD, int ST, bool DIFF, bool NT, bool BASIC = false>
-__global__ void __launch_bounds__(step_tiles_y(R) * NTHREADS) step_kernel(const StepArgs a) {
-  constexpr int K = step_tiles_y(R);
+// K one-step tiles per workgroup along y (the launch passes a.tiles_y == K)
+template <int R, bool GRAD, int ST, bool DIFF, bool NT, bool BASIC, int K>
+__global__ void __launch_bounds__(K * NTHREADS) step_kernel(const StepArgs a) {
   constexpr int NTH = K * NTHREADS;
   // Per-level scales of reduced-precision storage: decode cur and prev, choose
   // the encode scales of the level written here from the previous maxima.
@@ -812,13 +812,23 @@ int elementwise_blocks(int64_t n) {
   return (int)b;
 }
 
-template <int R, bool GRAD, int ST, bool DIFF, bool NT>
-hipError_t launch_r(const StepArgs& a, hipStream_t s) {
-  constexpr int nth = step_tiles_y(R) * NTHREADS;
+template <int R, bool GRAD, int ST, bool DIFF, bool NT, bool BASIC, int K>
+hipError_t launch_k(const StepArgs& a, hipStream_t s) {
+  constexpr int nth = K * NTHREADS;
   const int nsamp_blocks = a.samp_out != nullptr ? (a.nsamp + nth - 1) / nth : 0;
   const dim3 grid(a.nstencil_blocks + nsamp_blocks), block(nth);
-  hipLaunchKernelGGL((step_kernel<R, GRAD, ST, DIFF, NT>), grid, block, 0, s, a);
+  hipLaunchKernelGGL((step_kernel<R, GRAD, ST, DIFF, NT, BASIC, K>), grid, block, 0, s, a);
   return hipGetLastError();
+}
+
+// the workgroup height the host chose (a.tiles_y), instantiated where tall_tiles_ok
+template <int R, bool GRAD, int ST, bool DIFF, bool NT, bool BASIC = false>
+hipError_t launch_r(const StepArgs& a, hipStream_t s) {
+  if constexpr (tall_tiles_ok(R)) {
+    if (a.tiles_y == 2) return launch_k<R, GRAD, ST, DIFF, NT, BASIC, 2>(a, s);
+  }
+  if (a.tiles_y != 1) return hipErrorInvalidValue;
+  return launch_k<R, GRAD, ST, DIFF, NT, BASIC, 1>(a, s);
 }
 
 template <int R, int ST, bool DIFF>
@@ -844,18 +854,13 @@ hipError_t launch_variant(const StepArgs& a, bool grad, int st, bool diff, bool 
 }  // namespace
 
 hipError_t launch_step_basic(const StepArgs& a, int r, hipStream_t s) {
-  if (r < 1 || r > MAXR) return hipErrorInvalidValue;
-  const int nth = step_tiles_y(r) * NTHREADS;
-  const int nsb = a.samp_out != nullptr ? (a.nsamp + nth - 1) / nth : 0;
-  const dim3 grid(a.nstencil_blocks + nsb), block(nth);
   switch (r) {
-    case 4: hipLaunchKernelGGL((step_kernel<4, false, ST_F32, false, false, true>), grid, block, 0, s, a); break;
-    case 6: hipLaunchKernelGGL((step_kernel<6, false, ST_F32, false, false, true>), grid, block, 0, s, a); break;
-    case 8: hipLaunchKernelGGL((step_kernel<8, false, ST_F32, false, false, true>), grid, block, 0, s, a); break;
-    case 12: hipLaunchKernelGGL((step_kernel<12, false, ST_F32, false, false, true>), grid, block, 0, s, a); break;
+    case 4: return launch_r<4, false, ST_F32, false, false, true>(a, s);
+    case 6: return launch_r<6, false, ST_F32, false, false, true>(a, s);
+    case 8: return launch_r<8, false, ST_F32, false, false, true>(a, s);
+    case 12: return launch_r<12, false, ST_F32, false, false, true>(a, s);
     default: return hipErrorInvalidValue;
   }
-  return hipGetLastError();
 }
 
 hipError_t launch_step(const StepArgs& a, int r, bool grad, int st, bool diff, bool nt,

@@ -20,7 +20,7 @@ STORE_F32, STORE_F16, STORE_BF16, STORE_DIFF = 0, 1, 2, 16
 MODE_FORWARD, MODE_ADJOINT, MODE_GRADIENT = 0, 1, 2
 # execution-path flags (kernels, launch shapes, cache hints; never the arithmetic)
 PATH_ONE_STEP, PATH_TWO_STEP, PATH_STREAM, PATH_CACHED, PATH_LINEAR = 1, 2, 4, 8, 16
-PATH_GRAPH, PATH_DIRECT = 32, 64
+PATH_GRAPH, PATH_DIRECT, PATH_TILE16, PATH_TILE32 = 32, 64, 128, 256
 
 # Entry points declared in include/wave.h.
 SYMBOLS = ["wave_cfl_dt_max", "wave_workspace_bytes", "wave_checkpoint_bytes", "wave_forward",

@@ -69,7 +69,7 @@ static void reference(const wave_grid& g, const Geom& G, const Tiling& T,
 
 static void check_tables(const wave_grid& g, int zchunk, const std::vector<double>& xyz) {
   const Geom G = make_geom(&g);
-  const Tiling T = make_tiling(G, zchunk, false);
+  const Tiling T = make_tiling(G, g.so / 2, 0, zchunk, false);
   const int np = (int)xyz.size() / 3;
   const Layout L = make_layout(&g, 0, np, WAVE_MODE_FORWARD, 0);
   const PointTables& P = L.pts[1];
@@ -139,7 +139,7 @@ static void check_tables(const wave_grid& g, int zchunk, const std::vector<doubl
 static void check_ext_tables(wave_grid g, int zchunk, const std::vector<double>& xyz) {
   const int r = g.so / 2;
   const Geom G = make_geom(&g);
-  const Tiling T = make_tiling(G, zchunk, false);
+  const Tiling T = make_tiling(G, r, 0, zchunk, false);
   const int np = (int)xyz.size() / 3;
   const Layout L = make_layout(&g, np, 0, WAVE_MODE_FORWARD, 0, true);
   CHECK(L.fused);
@@ -315,9 +315,9 @@ static void test_ext_tables() {
 }
 
 static void test_tiling() {
-  const auto zc = [](int n, bool naive16) {
+  const auto zc = [](int n, bool naive16, int r = 2, int path = 0) {
     wave_grid g = grid(n, n, n);
-    return make_tiling(make_geom(&g), 0, naive16);
+    return make_tiling(make_geom(&g), r, path, 0, naive16);
   };
   // about 512 workgroups of one long chunk each
   CHECK(zc(256, false).zchunk == 32 && zc(256, false).nblocks == 512);
@@ -331,6 +331,27 @@ static void test_tiling() {
   // naive 16-bit storage: chunks of at most 32 planes, ~20 for large grids
   CHECK(zc(256, true).zchunk == 32);
   CHECK(zc(512, true).zchunk == 20);
+  // workgroup height of the one-step kernel: 64 x 32 tiles where the radius has
+  // them and their count is a multiple of the 256 CUs
+  CHECK(zc(256, false).tiles_y == 1);            // radius 2: 64 x 16 only
+  CHECK(zc(256, false, 4).tiles_y == 2);         // 4 x 8 x 8 = 256 tall workgroups
+  CHECK(zc(512, false, 4).tiles_y == 2);         // 8 x 16 x 2 = 256
+  CHECK(zc(320, false, 4).tiles_y == 1);         // 5 x 10 x 5 = 250
+  CHECK(zc(384, false, 4).tiles_y == 1);         // 6 x 12 x 3 = 216
+  CHECK(zc(448, false, 4).tiles_y == 1);         // 7 x 14 x 2 = 196
+  CHECK(zc(128, false, 8).tiles_y == 2);         // 2 x 4 x 32 = 256 (4-plane chunks)
+  CHECK(zc(96, false, 4).tiles_y == 1);          // 2 x 3 x 32 = 192
+  {
+    wave_grid g = grid(256, 144, 256);             // 4 x 5 x 14 = 280 (uneven)
+    CHECK(make_tiling(make_geom(&g), 4, 0, 0, false).tiles_y == 1);
+    g = grid(256, 256, 512);                       // 4 x 8 x 8 = 256 (64-plane chunks)
+    CHECK(make_tiling(make_geom(&g), 4, 0, 0, false).tiles_y == 2);
+  }
+  CHECK(zc(256, false, 8).tiles_y == 2 && zc(256, false, 10).tiles_y == 2);
+  CHECK(zc(256, false, 6).tiles_y == 1 && zc(256, false, 12).tiles_y == 1);
+  CHECK(zc(64, false, 4, WAVE_PATH_TILE32).tiles_y == 2);
+  CHECK(zc(64, false, 6, WAVE_PATH_TILE32).tiles_y == 1);  // no 64 x 32 form at radius 6
+  CHECK(zc(256, false, 4, WAVE_PATH_TILE16).tiles_y == 1);
   for (int n : {40, 97, 200, 333, 700}) {
     const Tiling T = zc(n, false);
     CHECK(T.zchunk >= 1 && T.zchunk <= MAXZCHUNK && T.zchunk <= n);

@@ -144,14 +144,15 @@ def test_path_flags_validated():
     variable changes a call): contradictory or unknown flags and chunk lengths out
     of 0..256 are rejected before anything is enqueued."""
     for bad in (wave.PATH_ONE_STEP | wave.PATH_TWO_STEP, wave.PATH_STREAM | wave.PATH_CACHED,
-                wave.PATH_GRAPH | wave.PATH_DIRECT, 128, -1):
+                wave.PATH_GRAPH | wave.PATH_DIRECT, wave.PATH_TILE16 | wave.PATH_TILE32, 512, -1):
         assert _fwd(_grid(path=bad)) == wave.EINVAL, bad
     for zc in (-1, 257):
         assert _fwd(_grid(zchunk=zc)) == wave.EINVAL, zc
     assert wave.workspace_bytes(_grid(zchunk=300), 0, 0) == 0
     # valid flags pass validation (the call then fails on the workspace size)
     for ok in (wave.PATH_ONE_STEP, wave.PATH_TWO_STEP | wave.PATH_STREAM | wave.PATH_LINEAR,
-               wave.PATH_CACHED | wave.PATH_GRAPH, wave.PATH_DIRECT):
+               wave.PATH_CACHED | wave.PATH_GRAPH, wave.PATH_DIRECT, wave.PATH_TILE16,
+               wave.PATH_TILE32 | wave.PATH_ONE_STEP):
         g = _grid(path=ok, zchunk=7)
         assert _fwd(g, wsb=wave.workspace_bytes(g, 0, 0) - 1) == wave.ENOMEM
 

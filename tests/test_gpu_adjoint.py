@@ -14,6 +14,7 @@ from helpers import ragged_case, rel_l2
 from paper_1912_00695_amd import inputs
 
 pytestmark = pytest.mark.gpu
+TALL = (8, 16, 20)  # orders with 64 x 32 workgroup tiles (WAVE_PATH_TILE32)
 
 
 def _dev():
@@ -39,6 +40,11 @@ def test_adjoint_matches_oracle(so):
     e_l = rel_l2(out["lam_final"].cpu().numpy(), lam_o)
     print("SO", so, "src", e_s, "lambda0", e_l, flush=True)
     assert e_s <= 1e-5 and e_l <= 1e-5
+    if so in TALL:  # 64 x 32 workgroup tiles (the default on large grids): same bits
+        o2 = wave.adjoint(case.wgrid(path=wave.PATH_TILE32), _t(case.vel), _t(d), case.rec,
+                          case.src, want_final=True)
+        assert np.array_equal(o2["src"].cpu().numpy(), out["src"].cpu().numpy())
+        assert np.array_equal(o2["lam_final"].cpu().numpy(), out["lam_final"].cpu().numpy())
 
 
 def _dot(case, seed):
@@ -125,6 +131,12 @@ def test_gradient_matches_oracle(so, ckpt):
         out2 = wave.gradient(g, _t(case.vel), _t(case.wavelet), case.src, case.rec, _t(resid),
                              ckpt=None, ckpt_every=ckpt)
         assert np.array_equal(out2["grad_vel"].cpu().numpy(), out["grad_vel"].cpu().numpy())
+    if so in TALL:  # 64 x 32 workgroup tiles: same bits
+        out3 = wave.gradient(case.wgrid(path=wave.PATH_TILE32), _t(case.vel), _t(case.wavelet),
+                             case.src, case.rec, _t(resid), ckpt=ck, ckpt_every=ckpt)
+        assert np.array_equal(out3["grad_vel"].cpu().numpy(), out["grad_vel"].cpu().numpy())
+        assert np.array_equal(out3["grad_wavelet"].cpu().numpy(),
+                              out["grad_wavelet"].cpu().numpy())
 
 
 def test_gradient_finite_differences_c3():

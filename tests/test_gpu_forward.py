@@ -60,6 +60,10 @@ def test_ragged_multitile(so):
     print("SO", so, "field", e_u, "traces", e_r)
     assert e_u <= TOL and e_r <= TOL
     assert max_rel(g["u_final"], uf) <= 1e-4 and max_rel(g["rec"], rec) <= 1e-4
+    if so in (8, 16, 20):  # 64 x 32 workgroup tiles (two tiles along y, the last half
+        from paper_1912_00695_amd import wave  # empty): the same bits as 64 x 16
+        t = _run(case, path=wave.PATH_TILE32)
+        assert np.array_equal(t["u_final"], g["u_final"]) and np.array_equal(t["rec"], g["rec"])
 
 
 @pytest.mark.parametrize("so", [2, 4, 8, 12, 16, 24])
@@ -287,11 +291,12 @@ def test_concurrent_calls_on_two_streams():
 @pytest.mark.parametrize("so", [8, 16, 20])
 def test_tall_tiles_sources_on_tile_edges(so):
     """Sources and receivers on and next to the edges of one-step tiles (y = 15 / 16,
-    47 / 48) and of the two-tile workgroup tiles that SO16 and SO20 use (y = 31 / 32,
-    63 / 64), on x-tile edges (63 / 64) and z-chunk edges (8-plane chunks), on a grid whose
-    last workgroup tile holds a single one-step tile (ny = 80): against the oracle, and
-    the same request through the serving engine (one-step tiles, the engine's own
-    chunking) bitwise against wave_forward."""
+    47 / 48) and of the two-tile workgroup tiles of SO8, SO16 and SO20 (y = 31 / 32,
+    63 / 64; forced with WAVE_PATH_TILE32, which the library takes by itself only on
+    grids with 256 or more such workgroups), on x-tile edges (63 / 64) and z-chunk edges
+    (8-plane chunks), on a grid whose last workgroup tile holds a single one-step tile
+    (ny = 80): against the oracle; the 64 x 16 tiling and the same request through the
+    serving engine (one-step tiles, the engine's own chunking) bitwise against it."""
     import torch
     from helpers import Case
     from paper_1912_00695_amd import inputs, serving, wave
@@ -304,13 +309,15 @@ def test_tall_tiles_sources_on_tile_edges(so):
     case.wavelet = np.random.default_rng(71).standard_normal((case.nt, len(pts))).astype(np.float32)
     case.rec = np.concatenate([case.src, inputs.random_points(n, h, 40, 72)])
     print("tall tiles: SO", so, "edge sources", flush=True)
-    g = _run(case, zchunk=8)
+    g = _run(case, zchunk=8, path=wave.PATH_TILE32)
     rec, uf, _ = case.oracle_forward()
     e_u, e_r = rel_l2(g["u_final"], uf), rel_l2(g["rec"], rec)
     print("  field %.3e traces %.3e" % (e_u, e_r), flush=True)
     assert e_u <= TOL and e_r <= TOL
+    s = _run(case, zchunk=8, path=wave.PATH_TILE16)
+    assert np.array_equal(s["u_final"], g["u_final"]) and np.array_equal(s["rec"], g["rec"])
     dev = torch.device("cuda:0")
-    grid = case.wgrid()
+    grid = case.wgrid(path=wave.PATH_TILE32)
     f = wave.forward(grid, torch.from_numpy(case.vel).to(dev),
                      torch.from_numpy(case.wavelet).to(dev), case.src, case.rec)["rec"].cpu().numpy()
     with serving.Engine(4 << 30, 4) as eng:
