@@ -118,7 +118,7 @@ Tiling make_tiling(const Geom& G, int r, int path, int zchunk, bool short_chunks
   T.nblocks = bxy * T.nchunk;
   // Workgroup height of the one-step kernel: two one-step tiles along y where the
   // radius has that form and the taller workgroups fill the 256 CUs evenly (a
-  // multiple of 256). Measured at SO8 with the chunks above: 256^3 +6.6 % and 512^3
+  // multiple of 256). Measured at SO8 with the chunks above: 256^3 +6.7 % and 512^3
   // +2.2 % (256 workgroups each); 320^3 -6 %, 384^3 -6 %, 448^3 -4 % (250, 216 and 196
   // workgroups: idle CUs). Uneven counts are worse still: a CU given two of them runs
   // out of VALU issue (the kernel keeps about 45 % of it busy at SO8): 288 workgroups

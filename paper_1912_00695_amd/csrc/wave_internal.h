@@ -21,12 +21,13 @@ constexpr int MAXZCHUNK = 256;   // planes per z-chunk at most (<= NTHREADS)
 // 1 (TX x TY points, NTHREADS threads) or 2 (TX x 2TY points, twice the threads:
 // half the y-halo per point). The taller tile exists for the radii whose bit is set
 // in WAVE_TALL_MASK; the host picks it per call (StepArgs::tiles_y) where the grid
-// still gives every CU a workgroup. The injection tables stay in TY-row tiles; a
-// taller tile reads them per sub-tile. Measured at 256^3 (one 512-thread workgroup
-// per CU instead of two of 256): SO8 +5.5 %, SO16 +2.5 %, SO20 +2.2 %; SO18 -6.7 %,
-// SO22 -4.8 %, SO24 -3.3 %.
+// fills the CUs evenly with it. The injection tables stay in TY-row tiles; a taller
+// tile reads them per sub-tile. Measured at 256^3 (one 512-thread workgroup per CU
+// instead of two of 256): SO2 +1.5 %, SO4 +2.9 %, SO6 +2.9 %, SO8 +6.7 %, SO16
+// +2.2 %, SO20 +1.8 %; SO14 level; SO10 -2.7 %, SO12 -2.9 %, SO18 -6.4 %, SO22
+// -4.7 %, SO24 -3.6 %.
 #ifndef WAVE_TALL_MASK
-#define WAVE_TALL_MASK 0x510  // radius 4, 8 and 10
+#define WAVE_TALL_MASK 0x51E  // radius 1-4, 8 and 10
 #endif
 constexpr bool tall_tiles_ok(int r) { return (((WAVE_TALL_MASK) >> r) & 1) != 0; }
 constexpr int SAMPLE_THREADS = 256;

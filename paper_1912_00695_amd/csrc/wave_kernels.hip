@@ -37,9 +37,9 @@ namespace wave {
 #endif
 // bit R of WAVE_ZUNROLL4_MASK: four planes per loop iteration, so the register
 // queue shifts once per four planes (fewer moves per plane, more code); measured
-// at 256^3: +3 % at SO16 and SO24, none at SO12, -1 % at SO8
+// at 256^3: +3 % at SO14, SO16 and SO24, none at SO12, -1 % at SO8
 #ifndef WAVE_ZUNROLL4_MASK
-#define WAVE_ZUNROLL4_MASK 0x1F00  // radius 8..12
+#define WAVE_ZUNROLL4_MASK 0x1F80  // radius 7..12
 #endif
 // bit R of WAVE_HRING_MASK: load the xy-halo of each plane R planes ahead (with the
 // queue head of the same plane) and park it in LDS until the plane is staged; by

@@ -333,7 +333,8 @@ static void test_tiling() {
   CHECK(zc(512, true).zchunk == 20);
   // workgroup height of the one-step kernel: 64 x 32 tiles where the radius has
   // them and their count is a multiple of the 256 CUs
-  CHECK(zc(256, false).tiles_y == 1);            // radius 2: 64 x 16 only
+  CHECK(zc(256, false).tiles_y == 2);            // radius 2: 4 x 8 x 8 = 256
+  CHECK(zc(256, false, 5).tiles_y == 1);         // radius 5: 64 x 16 only
   CHECK(zc(256, false, 4).tiles_y == 2);         // 4 x 8 x 8 = 256 tall workgroups
   CHECK(zc(512, false, 4).tiles_y == 2);         // 8 x 16 x 2 = 256
   CHECK(zc(320, false, 4).tiles_y == 1);         // 5 x 10 x 5 = 250

@@ -14,7 +14,7 @@ from helpers import ragged_case, rel_l2
 from paper_1912_00695_amd import inputs
 
 pytestmark = pytest.mark.gpu
-TALL = (8, 16, 20)  # orders with 64 x 32 workgroup tiles (WAVE_PATH_TILE32)
+TALL = (2, 4, 6, 8, 16, 20)  # orders with 64 x 32 workgroup tiles (WAVE_PATH_TILE32)
 
 
 def _dev():

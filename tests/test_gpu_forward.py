@@ -60,7 +60,7 @@ def test_ragged_multitile(so):
     print("SO", so, "field", e_u, "traces", e_r)
     assert e_u <= TOL and e_r <= TOL
     assert max_rel(g["u_final"], uf) <= 1e-4 and max_rel(g["rec"], rec) <= 1e-4
-    if so in (8, 16, 20):  # 64 x 32 workgroup tiles (two tiles along y, the last half
+    if so in (2, 4, 6, 8, 16, 20):  # 64 x 32 workgroup tiles (two tiles along y, the last half
         from paper_1912_00695_amd import wave  # empty): the same bits as 64 x 16
         t = _run(case, path=wave.PATH_TILE32)
         assert np.array_equal(t["u_final"], g["u_final"]) and np.array_equal(t["rec"], g["rec"])
@@ -288,10 +288,10 @@ def test_concurrent_calls_on_two_streams():
         assert np.array_equal(o["u_final"].cpu().numpy(), alone[k]["u_final"])
 
 
-@pytest.mark.parametrize("so", [8, 16, 20])
+@pytest.mark.parametrize("so", [4, 8, 16, 20])
 def test_tall_tiles_sources_on_tile_edges(so):
     """Sources and receivers on and next to the edges of one-step tiles (y = 15 / 16,
-    47 / 48) and of the two-tile workgroup tiles of SO8, SO16 and SO20 (y = 31 / 32,
+    47 / 48) and of the two-tile workgroup tiles of SO4, SO8, SO16 and SO20 (y = 31 / 32,
     63 / 64; forced with WAVE_PATH_TILE32, which the library takes by itself only on
     grids with 256 or more such workgroups), on x-tile edges (63 / 64) and z-chunk edges
     (8-plane chunks), on a grid whose last workgroup tile holds a single one-step tile
