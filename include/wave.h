@@ -102,7 +102,8 @@ extern "C" {
 #define WAVE_PATH_DIRECT 64   /* always launch directly (no graph)                     */
 /* Workgroup tile of the one-step kernel: 64 x 16 points, or 64 x 32 at SO 2, 4, 6, 8,
  * 16 and 20 (the orders that have it). By default the taller tile is taken at those
- * orders when its workgroups fill the GPU's 256 CUs evenly (a multiple of 256). */
+ * orders with FP32 storage when its workgroups fill the GPU's 256 CUs evenly (a
+ * multiple of 256). */
 #define WAVE_PATH_TILE16 128  /* 64 x 16 tiles                                         */
 #define WAVE_PATH_TILE32 256  /* 64 x 32 tiles at SO 2, 4, 6, 8, 16 and 20             */
 

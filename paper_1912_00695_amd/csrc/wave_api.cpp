@@ -95,7 +95,9 @@ Geom make_geom(const wave_grid* g) {
 // would need more than 1024 workgroups at 32 planes: 546 Gpt/s at 512^3 SO8 against
 // 498 with one long chunk per workgroup. A positive zchunk fixes the chunk length
 // (the grid's zchunk, or the caller's policy).
-Tiling make_tiling(const Geom& G, int r, int path, int zchunk, bool short_chunks) {
+Tiling make_tiling(const Geom& G, int r, int path, int zchunk, int storage) {
+  const int kind = storage & ~WAVE_STORE_DIFF;
+  const bool short_chunks = kind != WAVE_STORE_F32 && !(storage & WAVE_STORE_DIFF);
   Tiling T;
   T.ntile_x = (G.nx + TX - 1) / TX;
   T.ntile_y = (G.ny + TY - 1) / TY;
@@ -122,11 +124,15 @@ Tiling make_tiling(const Geom& G, int r, int path, int zchunk, bool short_chunks
   // +2.2 % (256 workgroups each); 320^3 -6 %, 384^3 -6 %, 448^3 -4 % (250, 216 and 196
   // workgroups: idle CUs). Uneven counts are worse still: a CU given two of them runs
   // out of VALU issue (the kernel keeps about 45 % of it busy at SO8): 288 workgroups
-  // at 384^3 (96-plane chunks) -23 %.
+  // at 384^3 (96-plane chunks) -23 %. With 16-bit storage (2-byte halos) the taller
+  // tiles do not pay: 512^3 SO8 -0.5 % in the difference form, -2.3 % naive (FP32
+  // +3 %), so those keep 64 x 16 unless WAVE_PATH_TILE32 asks.
   T.tiles_y = 1;
   if (tall_tiles_ok(r) && !(path & WAVE_PATH_TILE16)) {
     const int64_t tall = (int64_t)T.ntile_x * ((T.ntile_y + 1) / 2) * T.nchunk;
-    if ((path & WAVE_PATH_TILE32) || (tall >= kCUs && tall % kCUs == 0)) T.tiles_y = 2;
+    if ((path & WAVE_PATH_TILE32) ||
+        (kind == WAVE_STORE_F32 && tall >= kCUs && tall % kCUs == 0))
+      T.tiles_y = 2;
   }
   return T;
 }
@@ -554,8 +560,7 @@ int init_ctx(Ctx& C, const wave_grid* g, int nsrc, int nrec, int mode, int ckpt_
              size_t ws_bytes, void* stream, int zchunk, bool fused_levels) {
   C.g = g;
   C.G = make_geom(g);
-  C.T = make_tiling(C.G, g->so / 2, g->path, zchunk > 0 ? zchunk : g->zchunk,
-                    store_kind(g) != WAVE_STORE_F32 && !store_diff(g));
+  C.T = make_tiling(C.G, g->so / 2, g->path, zchunk > 0 ? zchunk : g->zchunk, g->storage);
   C.L = make_layout(g, nsrc, nrec, mode, ckpt_every, fused_levels);
   if (ws == nullptr || (reinterpret_cast<uintptr_t>(ws) % kAlign) != 0) return WAVE_EINVAL;
   if (ws_bytes < C.L.total) return WAVE_ENOMEM;

@@ -98,9 +98,10 @@ bool grid_ok(const wave_grid* g);
 int validate(const wave_grid* g);  // grid_ok + stability limit
 bool points_ok(const wave_grid* g, const double* xyz, int np);
 Geom make_geom(const wave_grid* g);
-// zchunk > 0 fixes the z-chunk length; 0 applies the single-solve policy. r and path
-// (WAVE_PATH_* flags) choose the one-step kernel's workgroup height.
-Tiling make_tiling(const Geom& G, int r, int path, int zchunk, bool short_chunks);
+// zchunk > 0 fixes the z-chunk length; 0 applies the single-solve policy (which
+// depends on the storage, WAVE_STORE_* flags). r, path (WAVE_PATH_* flags) and the
+// storage choose the one-step kernel's workgroup height.
+Tiling make_tiling(const Geom& G, int r, int path, int zchunk, int storage);
 // fused_levels: an FP32 forward layout at radius <= 4 also holds the two-step
 // kernel's two extra levels and extended-tile tables (false: one-step only)
 Layout make_layout(const wave_grid* g, int nsrc, int nrec, int mode, int ckpt_every,

@@ -69,7 +69,7 @@ static void reference(const wave_grid& g, const Geom& G, const Tiling& T,
 
 static void check_tables(const wave_grid& g, int zchunk, const std::vector<double>& xyz) {
   const Geom G = make_geom(&g);
-  const Tiling T = make_tiling(G, g.so / 2, 0, zchunk, false);
+  const Tiling T = make_tiling(G, g.so / 2, 0, zchunk, WAVE_STORE_F32);
   const int np = (int)xyz.size() / 3;
   const Layout L = make_layout(&g, 0, np, WAVE_MODE_FORWARD, 0);
   const PointTables& P = L.pts[1];
@@ -139,7 +139,7 @@ static void check_tables(const wave_grid& g, int zchunk, const std::vector<doubl
 static void check_ext_tables(wave_grid g, int zchunk, const std::vector<double>& xyz) {
   const int r = g.so / 2;
   const Geom G = make_geom(&g);
-  const Tiling T = make_tiling(G, r, 0, zchunk, false);
+  const Tiling T = make_tiling(G, r, 0, zchunk, WAVE_STORE_F32);
   const int np = (int)xyz.size() / 3;
   const Layout L = make_layout(&g, np, 0, WAVE_MODE_FORWARD, 0, true);
   CHECK(L.fused);
@@ -317,7 +317,7 @@ static void test_ext_tables() {
 static void test_tiling() {
   const auto zc = [](int n, bool naive16, int r = 2, int path = 0) {
     wave_grid g = grid(n, n, n);
-    return make_tiling(make_geom(&g), r, path, 0, naive16);
+    return make_tiling(make_geom(&g), r, path, 0, naive16 ? WAVE_STORE_F16 : WAVE_STORE_F32);
   };
   // about 512 workgroups of one long chunk each
   CHECK(zc(256, false).zchunk == 32 && zc(256, false).nblocks == 512);
@@ -344,9 +344,13 @@ static void test_tiling() {
   CHECK(zc(96, false, 4).tiles_y == 1);          // 2 x 3 x 32 = 192
   {
     wave_grid g = grid(256, 144, 256);             // 4 x 5 x 14 = 280 (uneven)
-    CHECK(make_tiling(make_geom(&g), 4, 0, 0, false).tiles_y == 1);
+    CHECK(make_tiling(make_geom(&g), 4, 0, 0, WAVE_STORE_F32).tiles_y == 1);
     g = grid(256, 256, 512);                       // 4 x 8 x 8 = 256 (64-plane chunks)
-    CHECK(make_tiling(make_geom(&g), 4, 0, 0, false).tiles_y == 2);
+    CHECK(make_tiling(make_geom(&g), 4, 0, 0, WAVE_STORE_F32).tiles_y == 2);
+    // 16-bit storage keeps 64 x 16 tiles unless asked
+    CHECK(make_tiling(make_geom(&g), 4, 0, 0, WAVE_STORE_F16 | WAVE_STORE_DIFF).tiles_y == 1);
+    CHECK(make_tiling(make_geom(&g), 4, 0, 0, WAVE_STORE_BF16).tiles_y == 1);
+    CHECK(make_tiling(make_geom(&g), 4, WAVE_PATH_TILE32, 0, WAVE_STORE_F16).tiles_y == 2);
   }
   CHECK(zc(256, false, 8).tiles_y == 2 && zc(256, false, 10).tiles_y == 2);
   CHECK(zc(256, false, 6).tiles_y == 1 && zc(256, false, 12).tiles_y == 1);
