@@ -297,8 +297,8 @@ def two_step_leg(dev):
         item["speedup"] = round(item["two_step_gpts"] / item["one_step_gpts"], 3)
         res["%d^3_so%d" % (n, so)] = item
         log("two-step %d^3 SO%d: %s" % (n, so, item))
-    res["default"] = ("two-step kernel used by default for SO2 from 3e7, SO4 from 6e7, SO6 "
-                      "from 8e7 and SO8 from 1.2e8 grid points")
+    res["default"] = ("two-step kernel used by default for SO2 from 3e7, SO4 from 6e7 and SO6 "
+                      "from 8e7 grid points; at SO8 only when asked (WAVE_PATH_TWO_STEP)")
     return res
 
 
@@ -647,19 +647,20 @@ def main():
             del S
         out["so_sweep_256"] = sweep
         # cache-defeating control: the one-step kernel at 512^3 (4 fields x 537 MB per
-        # step, far above the 256 MB Infinity Cache); the library's default path there
-        # is the two-step kernel, timed beside it
+        # step, far above the 256 MB Infinity Cache), the library's default path there;
+        # the two-step kernel timed beside it
         from paper_1912_00695_amd import wave as _w5
         ctl = {}
-        for key, path in (("gpts", _w5.PATH_ONE_STEP), ("default_path_gpts", 0)):
+        for key, path in (("gpts", _w5.PATH_ONE_STEP), ("two_step_gpts", _w5.PATH_TWO_STEP)):
             S = Solver(c2_problem(8, nt=500, n=(512, 512, 512), path=path), dev)
             e, _ = time_solves(S, 2, 0)
             ctl[key] = round(512 ** 3 * 500 * 2 / e / 1e9, 2)
             del S
-        out["control_512_so8"] = {"gpts": ctl["gpts"], "kernel": "step_kernel<4,false> (one step)",
+        out["control_512_so8"] = {"gpts": ctl["gpts"],
+                                  "kernel": "step_kernel<4,false> (one step, the default path)",
                                   "hbm_frac": round(ctl["gpts"] * ALG_BYTES_PER_PT / HBM_PEAK_GBS, 4),
-                                  "nt": 500, "default_path_gpts": ctl["default_path_gpts"],
-                                  "default_path": "two-step kernel, 128-plane chunks"}
+                                  "nt": 500, "two_step_gpts": ctl["two_step_gpts"],
+                                  "two_step": "two-step kernel, 128-plane chunks (forced)"}
         log("control 512^3 SO8: %s" % out["control_512_so8"])
     if not args.no_sweep:
         out["small_grids"] = small_grid_leg(dev)

@@ -355,19 +355,19 @@ void build_point_tables(const wave_grid* g, const Geom& G, const Tiling& T, cons
 bool fused_tiling_ok(const Ctx& C) { return C.L.fused && C.T.zchunk >= C.g->so; }
 
 // Whether an FP32 forward solve without checkpoints takes the two-step kernel, and
-// its z-chunk length. Measured on MI355X (64-plane chunks, cubic grids, two-step vs
-// the one-step kernel with its default tiling): SO2 +2 % at 320^3, +0 % at 384^3,
-// +22 % at 448^3, +34 % at 512^3; SO4 -15 % at 256^3, -4 % at 320^3, -6 % at 384^3,
-// +14 % at 448^3, +23 % at 512^3; SO6 -11 % at 320^3, -14 % at 384^3, +6 % at 448^3,
-// +11 % at 512^3. SO8 runs on tiles twice as tall (one 768-thread workgroup per
-// CU): +5 % at 512^3 with 128-plane chunks (512 workgroups; 64-plane chunks +2 %,
-// 32-plane -7 %), -2 % at 448^3 (64-plane chunks: 128 would leave 392 workgroups,
-// -18 %). Below these sizes the one-step kernel's working set is largely served by
-// the 256 MiB Infinity Cache; longer two-step chunks (128, 256 planes) lost at
+// its z-chunk length. Measured on MI355X (100-step solves, cubic grids, two-step vs
+// the one-step kernel with its default tiling, halo ring and hints): SO2 +2 % at
+// 384^3, +19 % at 512^3 (and +2 % at 320^3, +22 % at 448^3 against an earlier
+// one-step kernel); SO4 -8 % at 384^3, +12 % at 448^3, +12 % at 512^3; SO6 +1.5 % at
+// 448^3, +2.5 % at 512^3; SO8 (tiles twice as tall, one 768-thread workgroup per CU)
+// -8 % at 448^3, -3.5 % at 512^3, so at SO8 the one-step kernel is the default at
+// every size. Below these sizes the one-step kernel's working set is largely served
+// by the 256 MiB Infinity Cache; longer two-step chunks (128, 256 planes) lost at
 // SO2/SO4/SO6. Chosen by the library: at least kFusedMinPoints[r] grid points.
 // WAVE_PATH_TWO_STEP asks for it at radius <= 4, WAVE_PATH_ONE_STEP never takes it;
-// its z-chunks are the grid's zchunk, else fused_zchunk's.
-constexpr int64_t kFusedMinPoints[5] = {0, 30000000, 60000000, 80000000, 120000000};
+// its z-chunks are the grid's zchunk, else fused_zchunk's (at SO8 128-plane chunks
+// where they give 512 workgroups: +5 % over 64-plane chunks at 512^3).
+constexpr int64_t kFusedMinPoints[5] = {0, 30000000, 60000000, 80000000, INT64_MAX};
 constexpr int kFusedZChunk = 64;
 int fused_zchunk(const wave_grid* g) {
   const int r = g->so / 2;

@@ -42,14 +42,13 @@ namespace wave {
 #define WAVE_ZUNROLL4_MASK 0x1F80  // radius 7..12
 #endif
 // bit R of WAVE_HRING_MASK: load the xy-halo of each plane R planes ahead (with the
-// queue head of the same plane) and park it in LDS until the plane is staged; by
-// default only in launches without non-temporal streams (WAVE_HRING_NT=1: in those
-// too)
+// queue head of the same plane) and park it in LDS until the plane is staged, also
+// in launches with non-temporal streams (WAVE_HRING_NT=0: only in those without)
 #ifndef WAVE_HRING_MASK
 #define WAVE_HRING_MASK 0x1FE  // radius 1..8
 #endif
 #ifndef WAVE_HRING_NT
-#define WAVE_HRING_NT 0
+#define WAVE_HRING_NT 1
 #endif
 constexpr bool zunroll2(int r) { return ((WAVE_ZUNROLL_MASK) >> r) & 1; }
 constexpr bool prefetch2(int r) { return ((WAVE_PF2_MASK) >> r) & 1; }
@@ -92,8 +91,10 @@ __device__ __forceinline__ void step_tile(const StepArgs& a, const int xy, const
   // streaming (about R MB per XCD) between the two reads, more than L2 holds.
   // Measured on MI355X: +2 % (SO4) to +13 % (SO12) at 256^3, where every workgroup
   // of a step is resident at once. With non-temporal streams (grids whose step
-  // does not fit the Infinity Cache, swept in several rounds of workgroups) it
-  // ranged from +1 % to -8 % and is off.
+  // does not fit the Infinity Cache): 512^3 on 64 x 32 tiles SO2 / SO4 / SO8 / SO16
+  // +1.4 / +2.8 / +4.0 / +2.5 %, 384^3 and 448^3 SO8 (64 x 16 tiles) +2.9 and
+  // +5.4 %, the FP16 difference form at 512^3 +4 %; only 512^3 SO8 on 64 x 16 tiles
+  // lost (-0.7 %).
   constexpr bool HRG = halo_ring(R) && (!NT || WAVE_HRING_NT);
   constexpr bool BSTORE = bstore(R);
   using Raw = typename Store<ST>::Raw;

@@ -81,9 +81,10 @@ def test_full_size_c4_vs_oracle():
     smoothed-random 1500-4500 m/s, 40-cell sponge) against the FP64 oracle's result,
     stored by tests/golden/make_c4_reference.py (oracle traces of 256 receivers and
     u^1000 on a regular 64^3 sub-lattice; the sample's rel-L2 estimates the field's).
-    FP32 storage on the one-step kernel with non-temporal streams (as every 16-bit
-    format runs) and on the library's default path for this grid (the two-step
-    kernel, 128-plane chunks): rel-L2 <= 1e-5 and element-wise <= 1e-4 max|ref|;
+    FP32 storage on the one-step kernel with non-temporal streams (the library's
+    default for this grid, on 64 x 32 workgroup tiles; every 16-bit format runs this
+    kernel on 64 x 16 tiles) and on the two-step kernel (128-plane chunks): rel-L2 <=
+    1e-5 and element-wise <= 1e-4 max|ref|;
     FP16 difference form: <= 1e-2 on field and traces; every format's error against
     the oracle and against the FP32 one-step run is printed."""
     from paper_1912_00695_amd import wave
@@ -94,7 +95,7 @@ def test_full_size_c4_vs_oracle():
     o, st = 4, 8
     print("C4 512^3 SO8 nt=1000 against the stored oracle result", flush=True)
     res = {}
-    runs = [("f32", 0, wave.PATH_ONE_STEP), ("f32_default", 0, 0)] + \
+    runs = [("f32", 0, 0), ("f32_two_step", 0, wave.PATH_TWO_STEP)] + \
         [(k, v, 0) for k, v in FORMATS.items()]
     for name, storage, path in runs:
         r, u = _run(case, storage, path=path)
