@@ -356,10 +356,10 @@ bool fused_tiling_ok(const Ctx& C) { return C.L.fused && C.T.zchunk >= C.g->so; 
 
 // Whether an FP32 forward solve without checkpoints takes the two-step kernel, and
 // its z-chunk length. Measured on MI355X (100-step solves, cubic grids, two-step vs
-// the one-step kernel with its default tiling, halo ring and hints): SO2 +2 % at
-// 384^3, +19 % at 512^3 (and +2 % at 320^3, +22 % at 448^3 against an earlier
-// one-step kernel); SO4 -8 % at 384^3, +12 % at 448^3, +12 % at 512^3; SO6 +1.5 % at
-// 448^3, +2.5 % at 512^3; SO8 (tiles twice as tall, one 768-thread workgroup per CU)
+// the one-step kernel with its default tiling, halo ring and hints): SO2 +5 % at
+// 320^3, -2.4 % at 352^3, +2 % at 384^3, +19 % at 512^3; SO4 -5 % at 320^3, -8 % at
+// 384^3, +12 % at 416^3, 448^3 and 512^3; SO6 -15 % at 384^3, +1.7 % at 416^3, +1.5 %
+// at 448^3, +2.5 % at 512^3; SO8 (tiles twice as tall, one 768-thread workgroup per CU)
 // -8 % at 448^3, -3.5 % at 512^3, so at SO8 the one-step kernel is the default at
 // every size. Below these sizes the one-step kernel's working set is largely served
 // by the 256 MiB Infinity Cache; longer two-step chunks (128, 256 planes) lost at
