@@ -59,6 +59,11 @@ constexpr double kUpdateRate = 250e9;  // grid-point updates per second, for tha
 // 20.6 with 14-plane chunks); a group of several shots keeps long chunks, which
 // re-read fewer planes to prime their queues.
 constexpr int kChunkLens[] = {32, 24, 16, 12, 8, 6, 4, 3, 2, 1};
+// Cache groups whose 64 x 32 workgroups fill the CUs evenly are stepped on them.
+#ifndef WAVE_ENGINE_TALL
+#define WAVE_ENGINE_TALL 1
+#endif
+constexpr bool kEngineTall = WAVE_ENGINE_TALL != 0;
 constexpr int kEngineZChunk = 32;  // tiling of a shot's context (tables are chunk-free)
 // Shots stepped together in one run of kReplaySteps launches: their per-step arrays
 // (two levels and v^2 dt^2) fit the 256 MB Infinity Cache together, so they stay
@@ -86,7 +91,6 @@ struct Shot {
   int slot = -1;
   Ctx C{};
   size_t off_wav = 0, off_tr = 0;
-  int nsamp_blocks = 0;
   std::unique_ptr<Blob> blob;
   ShotDesc desc{};
   hipEvent_t ready = nullptr;
@@ -491,7 +495,6 @@ class Engine {
     d.nsrc = s->nsrc;
     d.nrec = s->nrec;
     d.nt = g->nt;
-    s->nsamp_blocks = s->nrec > 0 ? (s->nrec + NTHREADS - 1) / NTHREADS : 0;
     HIP_TRY(hipMemcpyAsync(d_desc_ + s->slot, &s->desc, sizeof(ShotDesc), hipMemcpyHostToDevice,
                            s_up_));
     HIP_TRY(hipMemcpyAsync(d_cnt_ + 2 * s->slot, s->cnt0, sizeof(s->cnt0), hipMemcpyHostToDevice,
@@ -512,7 +515,9 @@ class Engine {
       int r;
       size_t bytes;
       std::vector<Shot*> shots;
-      std::vector<BatchEntry> e;
+      std::vector<BatchEntry> e;  // stencil blocks of every shot, then sampling blocks
+      int nstencil = 0;
+      int ky = 1;  // workgroup height of the group's launches, in one-step tiles
     };
     const size_t gb = group_bytes_.load();
     const size_t cap = gb > 0 ? gb : kCacheGroupBytes;
@@ -544,24 +549,44 @@ class Engine {
           break;
         }
       }
-      // per shot: its stencil blocks chunk-major (the single-solve tile order), then
-      // its sampling blocks
+      // Workgroups of two one-step tiles along y (the single-solve rule): where the
+      // radius has them and the group's taller workgroups fill the CUs evenly, e.g. a
+      // 256^3 shot alone in its group, in 32-plane chunks (256 workgroups).
+      if (kEngineTall && tall_tiles_ok(G.r)) {
+        int64_t tall = 0;
+        for (const Shot* s : G.shots) {
+          const int z = s->g.zchunk > 0 ? s->g.zchunk : zc;
+          tall += (int64_t)s->C.T.ntile_x * ((s->C.T.ntile_y + 1) / 2) * ((s->g.nz + z - 1) / z);
+        }
+        if (tall >= kCUs && tall % kCUs == 0) G.ky = 2;
+      }
+      // every shot's stencil blocks chunk-major (the single-solve tile order), then
+      // every shot's sampling blocks
+      const int nth = G.ky * NTHREADS;
       for (Shot* s : G.shots) {
         const int z = s->g.zchunk > 0 ? s->g.zchunk : zc;
-        const int bxy = s->C.T.ntile_x * s->C.T.ntile_y;
+        const int bxy = s->C.T.ntile_x * ((s->C.T.ntile_y + G.ky - 1) / G.ky);
         const size_t e0 = G.e.size();
         for (int z0 = 0; z0 < s->g.nz; z0 += z)
           for (int xy = 0; xy < bxy; ++xy)
             G.e.push_back(BatchEntry{s->slot, xy, z0, std::min(z0 + z, s->g.nz)});
-        for (int k = 0; k < s->nsamp_blocks; ++k) G.e.push_back(BatchEntry{s->slot, -1 - k, 0, 0});
         s->entries = G.e.size() - e0;
       }
+      G.nstencil = (int)G.e.size();
+      for (Shot* s : G.shots) {
+        const int nsb = s->nrec > 0 ? (s->nrec + nth - 1) / nth : 0;
+        for (int k = 0; k < nsb; ++k) G.e.push_back(BatchEntry{s->slot, -1 - k, 0, 0});
+        s->entries += nsb;
+      }
     }
+    struct Seg {
+      int r, ky, off, count, nstencil;
+    };
     std::vector<BatchEntry> all;
-    std::vector<std::pair<int, std::pair<int, int>>> segs;  // radius, (offset, count)
+    std::vector<Seg> segs;
     graph_entries_ = 0;
     for (auto& G : groups) {
-      segs.push_back({G.r, {(int)all.size(), (int)G.e.size()}});
+      segs.push_back(Seg{G.r, G.ky, (int)all.size(), (int)G.e.size(), G.nstencil});
       all.insert(all.end(), G.e.begin(), G.e.end());
     }
     if ((int)all.size() > table_cap_) return WAVE_ENOMEM;
@@ -576,9 +601,9 @@ class Engine {
     hipGraph_t graph = nullptr;
     HIP_TRY(hipStreamBeginCapture(s_exec_, hipStreamCaptureModeThreadLocal));
     hipError_t err = hipSuccess;
-    for (auto& sg : segs)
+    for (const Seg& sg : segs)
       for (int k = 0; k < kReplaySteps && err == hipSuccess; ++k)
-        err = launch_batched(d_desc_, d_cnt_, tab + sg.second.first, sg.second.second, sg.first, k & 1,
+        err = launch_batched(d_desc_, d_cnt_, tab + sg.off, sg.count, sg.nstencil, sg.r, sg.ky, k & 1,
                              s_exec_);
     hipError_t e2 = hipStreamEndCapture(s_exec_, &graph);
     if (err != hipSuccess || e2 != hipSuccess) {

@@ -161,7 +161,8 @@ struct ShotDesc {
 // read-only in the kernel, so its arguments can be held like kernel arguments.
 struct BatchEntry {
   int shot;   // slot in the descriptor array
-  int xy;     // xy tile ty * ntile_x + tx of a stencil block, or -1-k for sampling block k
+  int xy;     // xy tile ty * ntile_x + tx of a stencil block (ty in rows of the launch's
+              // workgroup tiles), or -1-k for sampling block k
   int z0, z1; // the stencil block's planes [z0, z1) (at most MAXZCHUNK)
 };
 
@@ -175,9 +176,11 @@ hipError_t launch_step(const StepArgs& a, int r, bool grad, int st, bool diff, b
 hipError_t launch_step_basic(const StepArgs& a, int r, hipStream_t s);
 // two fused steps (radius r <= 4); nt: non-temporal stores of the two outputs
 hipError_t launch_fused2(const Fused2Args& f, int r, bool nt, hipStream_t s);
-// one batched step of every shot in table (space-order radius r, launch parity)
-hipError_t launch_batched(const ShotDesc* shots, int* cnts, const BatchEntry* table, int nentries, int r,
-                          int parity, hipStream_t s);
+// one batched step of every shot in table: nentries entries, the first nstencil of them
+// stencil blocks, then sampling blocks (space-order radius r, workgroups of tiles_y
+// one-step tiles along y: 1, or 2 where tall_tiles_ok(r); launch parity)
+hipError_t launch_batched(const ShotDesc* shots, int* cnts, const BatchEntry* table, int nentries,
+                          int nstencil, int r, int tiles_y, int parity, hipStream_t s);
 // out[i] = shots[slots[i]].cnt[0]
 hipError_t launch_gather_counters(const int* cnts, const int* slots, int n, int* out,
                                   hipStream_t s);

@@ -608,13 +608,18 @@ __global__ void __launch_bounds__(K * NTHREADS) step_kernel(const StepArgs a) {
 // The descriptors are read-only here (the counters are a separate array): with a
 // descriptor that the kernel also wrote, the compiler held its arguments in 19-38
 // more VGPRs than the single-shot kernel's (133 against 114 at r = 4, three waves per
-// SIMD instead of four); read-only, the two kernels use the same registers.
-template <int R>
-__global__ void __launch_bounds__(NTHREADS) batched_step_kernel(const ShotDesc* __restrict__ shots,
-                                                                int* __restrict__ cnts,
-                                                                const BatchEntry* __restrict__ table,
-                                                                int nentries, int parity) {
-  const int b = remap_tile(blockIdx.x, nentries);
+// SIMD instead of four); read-only, the two kernels use the same registers. K is the
+// launch's workgroup height in one-step tiles (the table's xy then counts K-tall
+// tiles). The table lists every stencil block before the sampling blocks, and only the
+// stencil blocks take the XCD remap, so the light sampling blocks are dispatched last
+// (a stencil block dispatched after every CU got one would run beside another on one
+// CU and hold up the launch: measured 6.7 % at SO8, 15 % at SO4 on 64 x 32 tiles).
+template <int R, int K>
+__global__ void __launch_bounds__(K * NTHREADS) batched_step_kernel(const ShotDesc* __restrict__ shots,
+                                                                    int* __restrict__ cnts,
+                                                                    const BatchEntry* __restrict__ table,
+                                                                    int nstencil, int parity) {
+  const int b = (int)blockIdx.x < nstencil ? remap_tile(blockIdx.x, nstencil) : (int)blockIdx.x;
   const BatchEntry e = table[b];
   const ShotDesc* sd = shots + e.shot;
   const int n = cnts[2 * e.shot + parity];
@@ -634,12 +639,13 @@ __global__ void __launch_bounds__(NTHREADS) batched_step_kernel(const ShotDesc* 
   }
   a.samp_out = (n >= 1 && sd->nrec > 0) ? sd->traces + (int64_t)(n - 1) * sd->nrec : nullptr;
   if (e.xy < 0) {
-    const int r = (-1 - e.xy) * NTHREADS + threadIdx.x;
+    const int r = (-1 - e.xy) * (K * NTHREADS) + threadIdx.x;
     if (a.samp_out != nullptr && r < a.nsamp)
       a.samp_out[r] = sample_point<ST_F32>(a.cur, 1.f, a.samp_idx, a.samp_w, r);
     return;
   }
-  if (n < nt) step_tile<R, false, ST_F32, false, false>(a, e.xy, e.z0, e.z1, 1.f, 1.f, 1.f, 1.f);
+  if (n < nt)
+    step_tile<R, false, ST_F32, false, false, false, K>(a, e.xy, e.z0, e.z1, 1.f, 1.f, 1.f, 1.f);
 }
 
 // Copy each listed shot's counter of parity 0 into out (host read-back after a replay).
@@ -883,26 +889,45 @@ hipError_t launch_step(const StepArgs& a, int r, bool grad, int st, bool diff, b
   }
 }
 
-hipError_t launch_batched(const ShotDesc* shots, int* cnts, const BatchEntry* table, int nentries, int r,
-                          int parity, hipStream_t s) {
+namespace {
+template <int R, int K>
+hipError_t launch_batched_k(const ShotDesc* shots, int* cnts, const BatchEntry* table, int nentries,
+                            int nstencil, int parity, hipStream_t s) {
+  const dim3 grid(nentries), block(K * NTHREADS);
+  hipLaunchKernelGGL((batched_step_kernel<R, K>), grid, block, 0, s, shots, cnts, table, nstencil,
+                     parity);
+  return hipGetLastError();
+}
+template <int R>
+hipError_t launch_batched_r(const ShotDesc* shots, int* cnts, const BatchEntry* table, int nentries,
+                            int nstencil, int tiles_y, int parity, hipStream_t s) {
+  if constexpr (tall_tiles_ok(R)) {
+    if (tiles_y == 2) return launch_batched_k<R, 2>(shots, cnts, table, nentries, nstencil, parity, s);
+  }
+  if (tiles_y != 1) return hipErrorInvalidValue;
+  return launch_batched_k<R, 1>(shots, cnts, table, nentries, nstencil, parity, s);
+}
+}  // namespace
+
+hipError_t launch_batched(const ShotDesc* shots, int* cnts, const BatchEntry* table, int nentries,
+                          int nstencil, int r, int tiles_y, int parity, hipStream_t s) {
   if (nentries <= 0) return hipSuccess;
-  const dim3 grid(nentries), block(NTHREADS);
+  if (nstencil < 0 || nstencil > nentries) return hipErrorInvalidValue;
   switch (r) {
-    case 1: hipLaunchKernelGGL(batched_step_kernel<1>, grid, block, 0, s, shots, cnts, table, nentries, parity); break;
-    case 2: hipLaunchKernelGGL(batched_step_kernel<2>, grid, block, 0, s, shots, cnts, table, nentries, parity); break;
-    case 3: hipLaunchKernelGGL(batched_step_kernel<3>, grid, block, 0, s, shots, cnts, table, nentries, parity); break;
-    case 4: hipLaunchKernelGGL(batched_step_kernel<4>, grid, block, 0, s, shots, cnts, table, nentries, parity); break;
-    case 5: hipLaunchKernelGGL(batched_step_kernel<5>, grid, block, 0, s, shots, cnts, table, nentries, parity); break;
-    case 6: hipLaunchKernelGGL(batched_step_kernel<6>, grid, block, 0, s, shots, cnts, table, nentries, parity); break;
-    case 7: hipLaunchKernelGGL(batched_step_kernel<7>, grid, block, 0, s, shots, cnts, table, nentries, parity); break;
-    case 8: hipLaunchKernelGGL(batched_step_kernel<8>, grid, block, 0, s, shots, cnts, table, nentries, parity); break;
-    case 9: hipLaunchKernelGGL(batched_step_kernel<9>, grid, block, 0, s, shots, cnts, table, nentries, parity); break;
-    case 10: hipLaunchKernelGGL(batched_step_kernel<10>, grid, block, 0, s, shots, cnts, table, nentries, parity); break;
-    case 11: hipLaunchKernelGGL(batched_step_kernel<11>, grid, block, 0, s, shots, cnts, table, nentries, parity); break;
-    case 12: hipLaunchKernelGGL(batched_step_kernel<12>, grid, block, 0, s, shots, cnts, table, nentries, parity); break;
+    case 1: return launch_batched_r<1>(shots, cnts, table, nentries, nstencil, tiles_y, parity, s);
+    case 2: return launch_batched_r<2>(shots, cnts, table, nentries, nstencil, tiles_y, parity, s);
+    case 3: return launch_batched_r<3>(shots, cnts, table, nentries, nstencil, tiles_y, parity, s);
+    case 4: return launch_batched_r<4>(shots, cnts, table, nentries, nstencil, tiles_y, parity, s);
+    case 5: return launch_batched_r<5>(shots, cnts, table, nentries, nstencil, tiles_y, parity, s);
+    case 6: return launch_batched_r<6>(shots, cnts, table, nentries, nstencil, tiles_y, parity, s);
+    case 7: return launch_batched_r<7>(shots, cnts, table, nentries, nstencil, tiles_y, parity, s);
+    case 8: return launch_batched_r<8>(shots, cnts, table, nentries, nstencil, tiles_y, parity, s);
+    case 9: return launch_batched_r<9>(shots, cnts, table, nentries, nstencil, tiles_y, parity, s);
+    case 10: return launch_batched_r<10>(shots, cnts, table, nentries, nstencil, tiles_y, parity, s);
+    case 11: return launch_batched_r<11>(shots, cnts, table, nentries, nstencil, tiles_y, parity, s);
+    case 12: return launch_batched_r<12>(shots, cnts, table, nentries, nstencil, tiles_y, parity, s);
     default: return hipErrorInvalidValue;
   }
-  return hipGetLastError();
 }
 
 hipError_t launch_gather_counters(const int* cnts, const int* slots, int n, int* out,

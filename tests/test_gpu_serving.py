@@ -189,3 +189,60 @@ def test_cache_groups_give_identical_results():
     for a, b in zip(outs[None], outs["1"]):
         assert np.abs(a).max() > 0
         assert np.array_equal(a, b)
+
+
+def _tall_request(seed, nt=90):
+    """128^3 SO8 request whose cache group the engine steps in 64 x 32 workgroup tiles:
+    sources on and next to one-step and two-tile edges (x 63 / 64, y 15 / 16 and 31 /
+    32, z on 4- and 8-plane chunk edges), 700 receivers (two sampling workgroups of
+    512 threads)."""
+    from paper_1912_00695_amd import wave
+    rng = np.random.default_rng(seed)
+    n, h = (128, 128, 128), (10.0, 10.0, 10.0)
+    vel = inputs.layered(n, 3, 1500.0, 3500.0, seed=seed)
+    vmax = float(vel.max())
+    dt = 0.5 * wave.cfl_dt_max(8, vmax, h)
+    pts = [(63, 15, 32), (64, 16, 40), (63.5, 31.5, 47.5), (20.25, 32, 64),
+           (100, 47, 71), (float(rng.uniform(20, 100)), float(rng.uniform(20, 100)), 56.5)]
+    src = np.array([[p[0] * h[0], p[1] * h[1], p[2] * h[2]] for p in pts])
+    wav = rng.standard_normal((nt, len(pts))).astype(np.float32)
+    rec = np.concatenate([inputs.line_x(n, h, 64, 20), inputs.random_points(n, h, 572, seed + 1)])
+    grid = wave.make_grid(n, h, 8, dt, nt, (10,) * 6, vmax=vmax)
+    return {"grid": grid, "vel": vel, "wavelet": wav, "src": src, "rec": rec}
+
+
+def test_engine_tall_tile_groups():
+    """Cache groups whose 64 x 32 workgroups fill the 256 CUs evenly are stepped on
+    those tiles: two 128^3 SO8 shots in one group (8-plane chunks, 2 x 128 tall
+    workgroups, then both shots' sampling workgroups), then one alone (4-plane chunks,
+    256). Each result bitwise equals wave_forward on 64 x 32 and on 64 x 16 tiles; one
+    against the FP64 oracle (rel-L2 <= 1e-5)."""
+    import torch
+    from paper_1912_00695_amd import wave
+    reqs = [_tall_request(s) for s in (81, 82, 83)]
+    print("engine tall-tile groups: 2 x 128^3 SO8 together, then 1 alone", flush=True)
+    with _engine() as eng:
+        outs = [eng.submit(r["grid"], r["vel"], r["wavelet"], r["src"], r["rec"])
+                for r in reqs[:2]]
+        eng.drain(120)
+        outs.append(eng.submit(reqs[2]["grid"], reqs[2]["vel"], reqs[2]["wavelet"],
+                               reqs[2]["src"], reqs[2]["rec"]))
+        eng.drain(120)
+        assert all(eng.poll(i)[0] == 0 for i, _ in outs)
+    dev = torch.device("cuda:0")
+    for r, (_, o) in zip(reqs, outs):
+        assert np.abs(o).max() > 0
+        g = r["grid"]
+        for tile in (wave.PATH_TILE32, wave.PATH_TILE16):
+            g2 = wave.make_grid((g.nx, g.ny, g.nz), (g.hx, g.hy, g.hz), g.so, g.dt, g.nt,
+                                tuple(g.nbl), vmax=g.vmax, path=tile)
+            f = wave.forward(g2, torch.from_numpy(r["vel"]).to(dev),
+                             torch.from_numpy(r["wavelet"]).to(dev), r["src"], r["rec"])["rec"]
+            assert np.array_equal(f.cpu().numpy(), o), tile
+    g, r = reqs[2]["grid"], reqs[2]
+    og = oracle.Grid((g.nx, g.ny, g.nz), (g.hx, g.hy, g.hz), g.so, g.dt, g.nt,
+                     nbl=tuple(g.nbl), vmax=g.vmax)
+    orec, _, _ = oracle.forward(og, r["vel"], r["wavelet"], r["src"], r["rec"])
+    e = rel_l2(outs[2][1], orec)
+    print("  alone vs oracle: traces rel-L2 %.3e" % e, flush=True)
+    assert e <= 1e-5
